@@ -1,0 +1,255 @@
+/*
+ * bsm.h -- block-sparse multiply for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libbsm.so.  The library computes the local part of the blocked
+ * sparse matrix multiply described in "DBCSR: A Blocked Sparse Tensor Algebra
+ * Library" (Sivkov, Seewald, Lazzaro, Hutter, 2019):
+ *   - matrices are grids of small dense blocks kept in a blocked compressed
+ *     sparse row index (Sec. 2);
+ *   - C = C + A x B is computed as pairwise products of (m x k) and (k x n)
+ *     dense blocks organised in batches (Sec. 2), here extended to
+ *     C_out = beta*C_in + alpha*op(A).op(B) with a norm-based product filter;
+ *   - rectangular shapes, in particular the case where C is much smaller than
+ *     A and B (Sec. 3.1), run through the same row-wise product enumeration;
+ *   - tensor contractions are mapped onto the matrix multiply (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns bsm_status; BSM_OK (0) on success, a
+ *   negative code otherwise.  bsm_last_error() returns a message for the last
+ *   failing call on the calling thread.  Nothing throws across the ABI.
+ *   Arguments are validated on the host before any device work is queued; on
+ *   a validation error no output is written and nothing is leaked.
+ * Memory: "host" pointers are ordinary CPU memory, read or written before the
+ *   call returns.  "device" pointers are GPU memory on the context's device;
+ *   the caller owns all value buffers.  Patterns, plans and batches own their
+ *   index arrays (device memory from the context's caching allocator) until
+ *   destroyed.  bsm_*_destroy(NULL) is a no-op.
+ * Ordering: all device work is queued on the context's stream, in call order;
+ *   functions that return sizes synchronise that stream.  Asynchronous device
+ *   errors surface at the next synchronising call as BSM_E_DEVICE.
+ * Layout (a reading; the paper fixes none): block (i,j) of a matrix is a dense
+ *   row-major array of row_sizes[i] x col_sizes[j] float64 values; blocks are
+ *   packed one after another in canonical (row, column) order, so block
+ *   offsets are prefix sums of the block sizes in that order.  Offsets and
+ *   value counts are int64.
+ * Filter (a reading; the paper defines none): s(X) is the squared Frobenius
+ *   norm of a stored block, summed in a fixed order (lane l of 64 sums the
+ *   squares of elements l, l+64, ... in storage order; the 64 partial sums are
+ *   combined pairwise, lane l with lane l+h for h = 32,16,...,1; no fused
+ *   multiply-add).  Product (i,k,j) is kept unless s(A_ik)*s(B_kj) <
+ *   filter_eps*filter_eps (float64); NaN norms keep the product.  alpha does
+ *   not enter the test.  filter_eps == 0 keeps every product.
+ * Not thread-safe per context: calls on one context must not overlap.
+ */
+#ifndef BSM_H
+#define BSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bsm_status;
+#define BSM_OK 0
+#define BSM_E_INVALID -1     /* bad argument: NULL handle, negative size, bad flag */
+#define BSM_E_DUPLICATE -2   /* a block listed twice */
+#define BSM_E_SHAPE -3       /* block sizes of the operands do not conform */
+#define BSM_E_NOMEM -4       /* device or host allocation failed */
+#define BSM_E_DEVICE -5      /* HIP runtime error (launch, copy, async fault) */
+#define BSM_E_UNSUPPORTED -6 /* valid request outside what this build handles */
+
+#define BSM_PREC_FP64 0      /* float64 products, float64 accumulation */
+#define BSM_PREC_BF16X3 1    /* split precision: hh + hl + lh bf16 pieces */
+#define BSM_PREC_BF16X6 2    /* split precision: 3 pieces, 6 cross products */
+
+typedef struct bsm_ctx_s* bsm_ctx;
+typedef struct bsm_pattern_s* bsm_pattern;
+typedef struct bsm_plan_s* bsm_plan;
+typedef struct bsm_batch_s* bsm_batch;
+typedef struct bsm_tpattern_s* bsm_tpattern;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* bsm_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t bsm_version(void);
+
+/* ------------------------------------------------------------ context
+ * device: HIP device ordinal.  stream: a hipStream_t (NULL = the default
+ * stream) on which all work of this context is queued.  The context owns a
+ * caching allocator for index memory, released at destroy.
+ * device == -1 creates a host-only context: patterns can be created,
+ * validated and exported, every call that needs the GPU returns
+ * BSM_E_DEVICE. */
+bsm_status bsm_ctx_create(int32_t device, void* stream, bsm_ctx* out);
+/* Switch the stream; work already queued on the old stream is waited for. */
+bsm_status bsm_ctx_set_stream(bsm_ctx ctx, void* stream);
+/* Wait for the context's stream; reports asynchronous device errors. */
+bsm_status bsm_sync(bsm_ctx ctx);
+bsm_status bsm_ctx_destroy(bsm_ctx ctx);
+
+/* ------------------------------------------------------------ patterns
+ * Blocked CSR index of a matrix (Sec. 2).  All arrays are host arrays.
+ * nbr, nbc >= 0 block rows / columns; row_sizes[nbr], col_sizes[nbc] >= 1
+ * (and < 65536); nblk >= 0 blocks given as (blk_row[l], blk_col[l]) in any
+ * order.  perm_out (host, may be NULL) receives, for every input block l,
+ * its slot in canonical order, so the caller can pack its values.
+ * Errors: BSM_E_INVALID (sizes, indices out of range), BSM_E_DUPLICATE. */
+bsm_status bsm_pattern_create(bsm_ctx ctx, int32_t nbr, const int32_t* row_sizes,
+                              int32_t nbc, const int32_t* col_sizes, int64_t nblk,
+                              const int32_t* blk_row, const int32_t* blk_col,
+                              int64_t* perm_out, bsm_pattern* out);
+/* Sizes of a pattern: block rows, block columns, blocks, float64 values. */
+bsm_status bsm_pattern_info(bsm_pattern p, int32_t* nbr, int32_t* nbc, int64_t* nblk,
+                            int64_t* nvals);
+/* Canonical block list (host outputs of length nblk; any may be NULL). */
+bsm_status bsm_pattern_export(bsm_pattern p, int32_t* blk_row, int32_t* blk_col,
+                              int64_t* blk_off);
+bsm_status bsm_pattern_destroy(bsm_pattern p);
+
+/* Squared block norms s(X) of a pattern's blocks, in canonical order.
+ * vals: device, nvals float64 in canonical layout.  norms_out: device, nblk
+ * float64.  Definition and order: see "Filter" above. */
+bsm_status bsm_block_norms(bsm_ctx ctx, bsm_pattern p, const double* vals, double* norms_out);
+
+/* ------------------------------------------------------------ multiply
+ * Options: trans_a/trans_b (0/1) select op(X) = X^T (block (i,j) of X^T is the
+ * transpose of stored block (j,i); norms are those of the stored blocks);
+ * retain_sparsity (0/1) drops products whose output block is not in C_in;
+ * precision is one of BSM_PREC_*. */
+typedef struct bsm_mm_opts {
+  int32_t trans_a;
+  int32_t trans_b;
+  int32_t retain_sparsity;
+  int32_t precision;
+} bsm_mm_opts;
+
+/* Statistics of a plan. */
+typedef struct bsm_plan_info_t {
+  int64_t c_nblk;      /* blocks of C_out */
+  int64_t c_nvals;     /* float64 values of C_out */
+  int64_t nprod;       /* kept block products (stack entries) */
+  int64_t ncand;       /* candidate products before the filter */
+  int64_t flops;       /* useful flops: sum of 2*m*n*k over kept products */
+  int64_t ntasks;      /* numeric work items (output tiles) */
+  int32_t c_nbr, c_nbc;
+} bsm_plan_info_t;
+
+/* Symbolic phase: block norms (if filter_eps > 0), the kept product set and
+ * the output pattern pat(C_out) = pat(C_in) U {(i,j): some (i,k,j) kept}
+ * (= pat(C_in) with retain_sparsity), with C_out's own canonical offsets, and
+ * the per-output-block product lists ("stacks", ordered by k).
+ * A, B: patterns; a_vals, b_vals: device values, read only when
+ * filter_eps > 0 and the matching norms pointer is NULL.  a_norms, b_norms:
+ * device, optional precomputed bsm_block_norms output.  C_in: optional
+ * pattern (NULL = empty).  filter_eps: finite, >= 0.
+ * Sizes: op(A) column sizes must equal op(B) row sizes; C_in's sizes must
+ * match op(A) rows and op(B) columns (BSM_E_SHAPE).  Synchronises once to
+ * learn the output size.  The plan keeps references to A, B and C_in: they
+ * must outlive it. */
+bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals,
+                             const double* a_norms, bsm_pattern B, const double* b_vals,
+                             const double* b_norms, bsm_pattern C_in, double filter_eps,
+                             const bsm_mm_opts* opts, bsm_plan* out);
+bsm_status bsm_plan_info(bsm_plan plan, bsm_plan_info_t* info);
+/* New pattern handle for C_out (the caller destroys it). */
+bsm_status bsm_plan_c_pattern(bsm_plan plan, bsm_pattern* out);
+/* Kept products as canonical block indices into A, B and C_out (host outputs
+ * of length nprod, grouped by output block in canonical order, then k). */
+bsm_status bsm_plan_export_stack(bsm_plan plan, int64_t* a_blk, int64_t* b_blk,
+                                 int64_t* c_blk);
+/* Numeric phase: c_out = beta*c_in + alpha*sum(kept products), block by
+ * block on pat(C_out).  All pointers device.  c_in is read only if beta != 0
+ * (may then be NULL only when C_in is empty).  c_out (c_nvals values) may
+ * alias c_in only when pat(C_out) == pat(C_in); then, with beta == 1, output
+ * blocks without products are left untouched.  Each output element is
+ * written by exactly one lane: results are bit-identical run to run. */
+bsm_status bsm_plan_execute(bsm_plan plan, double alpha, const double* a_vals,
+                            const double* b_vals, double beta, const double* c_in_vals,
+                            double* c_out_vals);
+/* Plan + execute in one call for an output pattern the caller already knows
+ * (retain_sparsity, or C_in covering every product): c_out must hold
+ * pat(C_out) = pat(C_in) values; BSM_E_SHAPE if the product would add blocks. */
+bsm_status bsm_multiply(bsm_ctx ctx, double alpha, bsm_pattern A, const double* a_vals,
+                        bsm_pattern B, const double* b_vals, double beta, bsm_pattern C,
+                        const double* c_in_vals, double* c_out_vals, double filter_eps,
+                        const bsm_mm_opts* opts);
+/* Gradient of the plan's function with its kept set held fixed (not in the
+ * paper):  d op(A)_ik = alpha * sum_j dC_ij . op(B)_kj^T   on pat(A),
+ *          d op(B)_kj = alpha * sum_i op(A)_ik^T . dC_ij   on pat(B).
+ * dc_vals: device, pat(C_out) layout.  da_vals / db_vals: device outputs in
+ * the stored layout of A / B, overwritten (blocks without products get 0);
+ * either may be NULL to skip it.  dC_in = beta*dC is left to the caller.
+ * The first call builds the regrouped product lists and keeps them. */
+bsm_status bsm_plan_backward(bsm_plan plan, double alpha, const double* dc_vals,
+                             const double* a_vals, const double* b_vals, double* da_vals,
+                             double* db_vals);
+bsm_status bsm_plan_destroy(bsm_plan plan);
+
+/* ------------------------------------------------------------ batches
+ * Many independent multiplies of uneven sizes executed by one persistent
+ * kernel launch over a merged, cost-ordered work list (the batches of Sec. 2
+ * across problems).  plans: n plans of the same context (all fp64 or all of
+ * one split precision).  The batch keeps references to the plans. */
+bsm_status bsm_batch_create(bsm_ctx ctx, int32_t n, const bsm_plan* plans, bsm_batch* out);
+/* alpha, beta: host arrays of n scalars.  a_vals..c_out: host arrays of n
+ * device pointers (c_in entries may be NULL where beta is 0).
+ * use_graph != 0 captures the launch into a HIP graph on first use and
+ * replays it while the pointers and scalars are unchanged. */
+bsm_status bsm_batch_execute(bsm_batch batch, const double* alpha, const double* beta,
+                             const double* const* a_vals, const double* const* b_vals,
+                             const double* const* c_in_vals, double* const* c_out_vals,
+                             int32_t use_graph);
+bsm_status bsm_batch_destroy(bsm_batch batch);
+
+/* ------------------------------------------------------------ tensors
+ * Block-sparse tensor pattern (Sec. 4): rank 2..4; nblk_mode[d] blocks along
+ * mode d with sizes blk_sizes[d][0..nblk_mode[d]) (host arrays, each >= 1);
+ * nblocks blocks given as rank-tuples in blk_idx (host, nblocks x rank,
+ * row-major), any order.  A block is a dense row-major sub-tensor (last mode
+ * fastest); blocks are packed in lexicographic order of their indices.
+ * perm_out as for matrices. */
+bsm_status bsm_tpattern_create(bsm_ctx ctx, int32_t rank, const int32_t* nblk_mode,
+                               const int32_t* const* blk_sizes, int64_t nblocks,
+                               const int32_t* blk_idx, int64_t* perm_out, bsm_tpattern* out);
+bsm_status bsm_tpattern_info(bsm_tpattern t, int32_t* rank, int64_t* nblocks, int64_t* nvals);
+/* Canonical block list: blk_idx (nblocks x rank) and blk_off (host, may be NULL). */
+bsm_status bsm_tpattern_export(bsm_tpattern t, int32_t* blk_idx, int64_t* blk_off);
+bsm_status bsm_tpattern_destroy(bsm_tpattern t);
+
+/* Contraction plan (Sec. 4: contraction mapped onto the matrix multiply).
+ * spec: einsum-style, e.g. "mnP,nl->mlP": one letter per mode; a letter in
+ * both inputs and not in the output is summed; every other letter appears
+ * in one input and in the output.  Matricization: rows of T1 = its free modes
+ * in output order (first slowest), columns = the summed modes in T1 order;
+ * T2 rows = the summed modes, columns = its free modes in output order.  The
+ * block index map is computed from the tensor indices.  Layouts that already
+ * match the matricization (row-major, transposed, or the summed modes
+ * between two groups of free modes) are read and written in place; others
+ * are permuted by the remap kernel into scratch buffers at execute.
+ * T3_in: optional output pattern (NULL = empty).  The resulting plan is used
+ * with bsm_plan_execute / bsm_plan_backward / bsm_plan_info with tensor value
+ * buffers in the tensors' own layouts; bsm_plan_t3_pattern gives the output
+ * tensor pattern. */
+bsm_status bsm_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, const double* t1_vals,
+                             bsm_tpattern T2, const double* t2_vals, bsm_tpattern T3_in,
+                             double filter_eps, const bsm_mm_opts* opts, bsm_plan* out);
+bsm_status bsm_plan_t3_pattern(bsm_plan plan, bsm_tpattern* out);
+
+/* ------------------------------------------------------------ tuning
+ * Numeric-kernel variant table: for each output tile class (padded rows,
+ * padded columns in {8,16,24,32}) the variant index to use (0 = matrix-core
+ * 4x4x4 tile, 1 = matrix-core with LDS-staged operands); see bsm_tune_get.
+ * path: JSON file written by the tuner, or NULL to reset to built-in
+ * defaults. */
+bsm_status bsm_tune_load(const char* path);
+/* Current table: out[16] variant per class (row-major over padded rows,
+ * columns). */
+bsm_status bsm_tune_get(int32_t* out16);
+bsm_status bsm_tune_set(const int32_t* in16);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSM_H */

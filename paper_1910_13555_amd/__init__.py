@@ -1,0 +1,342 @@
+"""Block-sparse multiply on AMD MI355X: Python binding of libbsm.
+
+The library (include/bsm.h) computes the local block-sparse multiply of DBCSR
+(Sec. 2 of the paper), its rectangular shapes (Sec. 3) and tensor
+contractions mapped onto it (Sec. 4).  This package marshals arguments:
+patterns are built from numpy block lists, values live in torch float64 CUDA
+tensors (device memory and streams only), and every step of the multiply
+runs in the library's HIP kernels.
+
+Entry points mirror the C ABI names (``bsm_pattern_create``,
+``bsm_multiply_plan``, ``bsm_plan_execute``, ...); ``BlockSparseMatrix`` and
+``matmul`` add an autograd-aware convenience layer.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import weakref
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BsmError, MmOpts, PlanInfo, check, lib
+
+__all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmul",
+           "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
+           "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context"]
+
+
+_live = {"plan": weakref.WeakSet(), "pattern": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_all():
+    """Release library handles while the HIP runtime is still up."""
+    for kind in ("plan", "pattern", "ctx"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+def _ptr(t):
+    """Device address of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("values must be torch tensors")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("values must be contiguous float64 tensors")
+    if t.numel() and not t.is_cuda:
+        raise TypeError("values must live on the GPU")
+    return t.data_ptr() if t.numel() else None
+
+
+# ---------------------------------------------------------------- context
+
+class Context:
+    """A libbsm context bound to one device and one stream (default: torch's
+    current stream of that device).  device=-1 gives a host-only context."""
+
+    def __init__(self, device: int = 0, stream=None):
+        if device >= 0 and stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        check(lib.bsm_ctx_create(device, C.c_void_p(stream or 0), C.byref(h)))
+        self.handle = h
+        self.device = device
+        _live["ctx"].add(self)
+
+    def set_stream(self, stream):
+        check(lib.bsm_ctx_set_stream(self.handle, C.c_void_p(stream or 0)))
+
+    def sync(self):
+        check(lib.bsm_sync(self.handle))
+
+    def close(self):
+        if self.handle:
+            check(lib.bsm_ctx_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def default_context(device: int = 0) -> Context:
+    """One context per device on torch's current stream of that device."""
+    ctx = _default.get(device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    if ctx is None:
+        ctx = _default[device] = Context(device, stream)
+        ctx._stream = stream
+    elif ctx._stream != stream:
+        ctx.set_stream(stream)
+        ctx._stream = stream
+    return ctx
+
+
+def bsm_ctx_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+# ---------------------------------------------------------------- pattern
+
+class Pattern:
+    """Blocked CSR index (Sec. 2) of a matrix; canonical (row, col) order."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx, self.handle = ctx, handle
+        _live["pattern"].add(self)
+        nbr, nbc = C.c_int32(), C.c_int32()
+        nblk, nvals = C.c_int64(), C.c_int64()
+        check(lib.bsm_pattern_info(handle, C.byref(nbr), C.byref(nbc), C.byref(nblk), C.byref(nvals)))
+        self.nbr, self.nbc, self.nblk, self.nvals = nbr.value, nbc.value, nblk.value, nvals.value
+
+    def export(self):
+        rows = np.empty(self.nblk, np.int32)
+        cols = np.empty(self.nblk, np.int32)
+        offs = np.empty(self.nblk, np.int64)
+        check(lib.bsm_pattern_export(self.handle, _lib.as_i32p(rows), _lib.as_i32p(cols),
+                                     _lib.as_i64p(offs)))
+        return rows, cols, offs
+
+    def close(self):
+        if self.handle:
+            check(lib.bsm_pattern_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bsm_pattern_create(ctx: Context, row_sizes, col_sizes, rows, cols):
+    """Returns (Pattern, perm) with perm[l] = canonical slot of input block l."""
+    rs = np.ascontiguousarray(row_sizes, np.int32)
+    cs = np.ascontiguousarray(col_sizes, np.int32)
+    br = np.ascontiguousarray(rows, np.int32)
+    bc = np.ascontiguousarray(cols, np.int32)
+    if br.shape != bc.shape:
+        raise ValueError("rows and cols differ in length")
+    perm = np.empty(len(br), np.int64)
+    h = C.c_void_p()
+    check(lib.bsm_pattern_create(ctx.handle, len(rs), _lib.as_i32p(rs), len(cs), _lib.as_i32p(cs),
+                                 len(br), _lib.as_i32p(br), _lib.as_i32p(bc), _lib.as_i64p(perm),
+                                 C.byref(h)))
+    return Pattern(ctx, h), perm
+
+
+def bsm_block_norms(ctx: Context, pattern: Pattern, vals: torch.Tensor, out: torch.Tensor = None):
+    if out is None:
+        out = torch.empty(pattern.nblk, dtype=torch.float64, device=vals.device)
+    check(lib.bsm_block_norms(ctx.handle, pattern.handle, _ptr(vals), _ptr(out)))
+    return out
+
+
+# ------------------------------------------------------------------- plan
+
+class Plan:
+    """Symbolic result of a multiply: output pattern plus product stacks."""
+
+    def __init__(self, ctx, handle, refs):
+        self.ctx, self.handle, self._refs = ctx, handle, refs
+        _live["plan"].add(self)
+        info = PlanInfo()
+        check(lib.bsm_plan_info(handle, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+
+    def c_pattern(self) -> Pattern:
+        h = C.c_void_p()
+        check(lib.bsm_plan_c_pattern(self.handle, C.byref(h)))
+        return Pattern(self.ctx, h)
+
+    def export_stack(self):
+        n = self.info["nprod"]
+        a = np.empty(n, np.int64)
+        b = np.empty(n, np.int64)
+        c = np.empty(n, np.int64)
+        check(lib.bsm_plan_export_stack(self.handle, _lib.as_i64p(a), _lib.as_i64p(b), _lib.as_i64p(c)))
+        return a, b, c
+
+    def _check_sizes(self, a_vals, b_vals, c_in, out):
+        A, B, Cp = self._refs[:3]
+        if a_vals is not None and a_vals.numel() < A.nvals:
+            raise ValueError("a_vals holds fewer values than pattern A")
+        if b_vals is not None and b_vals.numel() < B.nvals:
+            raise ValueError("b_vals holds fewer values than pattern B")
+        if c_in is not None and Cp is not None and c_in.numel() < Cp.nvals:
+            raise ValueError("c_in holds fewer values than pattern C_in")
+        if out is not None and out.numel() < self.info["c_nvals"]:
+            raise ValueError("output holds fewer values than pattern C_out")
+
+    def execute(self, alpha, a_vals, b_vals, beta=0.0, c_in=None, out=None):
+        if out is None:
+            out = torch.empty(self.info["c_nvals"], dtype=torch.float64, device=a_vals.device)
+        self._check_sizes(a_vals, b_vals, c_in, out)
+        check(lib.bsm_plan_execute(self.handle, float(alpha), _ptr(a_vals), _ptr(b_vals), float(beta),
+                                   _ptr(c_in), _ptr(out)))
+        return out
+
+    def backward(self, alpha, dc, a_vals, b_vals, da=None, db=None):
+        self._check_sizes(a_vals, b_vals, None, dc)
+        self._check_sizes(da, db, None, None)
+        check(lib.bsm_plan_backward(self.handle, float(alpha), _ptr(dc), _ptr(a_vals), _ptr(b_vals),
+                                    _ptr(da), _ptr(db)))
+        return da, db
+
+    def close(self):
+        if self.handle:
+            check(lib.bsm_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(trans_a=False, trans_b=False, retain_sparsity=False, precision="fp64"):
+    return MmOpts(int(trans_a), int(trans_b), int(retain_sparsity), _lib.PREC[precision])
+
+
+def bsm_multiply_plan(ctx: Context, A: Pattern, a_vals, B: Pattern, b_vals, C_in: Pattern = None,
+                      filter_eps: float = 0.0, trans_a=False, trans_b=False, retain_sparsity=False,
+                      precision="fp64", a_norms=None, b_norms=None) -> Plan:
+    h = C.c_void_p()
+    o = _opts(trans_a, trans_b, retain_sparsity, precision)
+    check(lib.bsm_multiply_plan(ctx.handle, A.handle, _ptr(a_vals), _ptr(a_norms), B.handle,
+                                _ptr(b_vals), _ptr(b_norms), C_in.handle if C_in else None,
+                                float(filter_eps), C.byref(o), C.byref(h)))
+    return Plan(ctx, h, (A, B, C_in))
+
+
+def bsm_plan_execute(plan: Plan, alpha, a_vals, b_vals, beta=0.0, c_in=None, out=None):
+    return plan.execute(alpha, a_vals, b_vals, beta, c_in, out)
+
+
+def bsm_plan_backward(plan: Plan, alpha, dc, a_vals, b_vals, da=None, db=None):
+    return plan.backward(alpha, dc, a_vals, b_vals, da, db)
+
+
+def bsm_multiply(ctx: Context, alpha, A: Pattern, a_vals, B: Pattern, b_vals, beta, Cp: Pattern,
+                 c_in, c_out, filter_eps=0.0, trans_a=False, trans_b=False, retain_sparsity=False):
+    o = _opts(trans_a, trans_b, retain_sparsity)
+    check(lib.bsm_multiply(ctx.handle, float(alpha), A.handle, _ptr(a_vals), B.handle, _ptr(b_vals),
+                           float(beta), Cp.handle, _ptr(c_in), _ptr(c_out), float(filter_eps),
+                           C.byref(o)))
+    return c_out
+
+
+# ------------------------------------------------------- matrix + autograd
+
+class BlockSparseMatrix:
+    """Pattern plus a float64 value tensor in canonical block order."""
+
+    def __init__(self, pattern: Pattern, values: torch.Tensor, row_sizes, col_sizes):
+        if values.numel() != pattern.nvals:
+            raise ValueError(f"{values.numel()} values for a pattern of {pattern.nvals}")
+        self.pattern = pattern
+        self.values = values
+        self.row_sizes = np.asarray(row_sizes, np.int32)
+        self.col_sizes = np.asarray(col_sizes, np.int32)
+
+    @classmethod
+    def from_lists(cls, row_sizes, col_sizes, rows, cols, values, device=0, ctx=None):
+        """Blocks in any order; ``values`` holds them one after another
+        (row-major per block).  Values are packed into canonical order on the
+        host when the list is not already canonical."""
+        ctx = ctx or default_context(device)
+        pat, perm = bsm_pattern_create(ctx, row_sizes, col_sizes, rows, cols)
+        if isinstance(values, torch.Tensor):
+            vals = values.to(device=f"cuda:{device}", dtype=torch.float64).contiguous()
+        else:
+            vals = None
+        if not np.array_equal(perm, np.arange(len(perm))):
+            rs = np.asarray(row_sizes, np.int64)
+            cs = np.asarray(col_sizes, np.int64)
+            lens = rs[np.asarray(rows)] * cs[np.asarray(cols)]
+            src = np.concatenate([[0], np.cumsum(lens)])
+            host = values.cpu().numpy() if isinstance(values, torch.Tensor) else np.asarray(values)
+            order = np.argsort(perm)
+            packed = np.concatenate([host[src[l]:src[l + 1]] for l in order]) if len(order) else host[:0]
+            vals = torch.from_numpy(np.ascontiguousarray(packed, np.float64)).to(f"cuda:{device}")
+        elif vals is None:
+            vals = torch.from_numpy(np.ascontiguousarray(values, np.float64)).to(f"cuda:{device}")
+        return cls(pat, vals, row_sizes, col_sizes)
+
+    @classmethod
+    def from_workload(cls, d, device=0, ctx=None):
+        return cls.from_lists(d["row_sizes"], d["col_sizes"], d["rows"], d["cols"], d["values"],
+                              device, ctx)
+
+
+class _MatmulFn(torch.autograd.Function):
+    """Differentiable multiply: the backward reuses the forward's kept set."""
+
+    @staticmethod
+    def forward(ctx_, a_vals, b_vals, c_vals, plan, alpha, beta):
+        out = plan.execute(alpha, a_vals, b_vals, beta, c_vals)
+        ctx_.plan, ctx_.alpha, ctx_.beta = plan, alpha, beta
+        ctx_.has_c = c_vals is not None
+        ctx_.save_for_backward(a_vals, b_vals)
+        return out
+
+    @staticmethod
+    def backward(ctx_, g):
+        a_vals, b_vals = ctx_.saved_tensors
+        g = g.contiguous()
+        da = torch.empty_like(a_vals) if ctx_.needs_input_grad[0] else None
+        db = torch.empty_like(b_vals) if ctx_.needs_input_grad[1] else None
+        if da is not None or db is not None:
+            ctx_.plan.backward(ctx_.alpha, g, a_vals, b_vals, da, db)
+        dc = None
+        if ctx_.has_c and ctx_.needs_input_grad[2]:
+            dc = ctx_.plan.cin_grad(g, ctx_.beta)
+        return da, db, dc, None, None, None
+
+
+def matmul(A: BlockSparseMatrix, B: BlockSparseMatrix, C: BlockSparseMatrix = None, alpha=1.0,
+           beta=0.0, filter_eps=0.0, trans_a=False, trans_b=False, retain_sparsity=False,
+           precision="fp64") -> BlockSparseMatrix:
+    ctx = A.pattern.ctx
+    plan = bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values,
+                             C.pattern if C is not None else None, filter_eps, trans_a, trans_b,
+                             retain_sparsity, precision)
+    out = _MatmulFn.apply(A.values, B.values, C.values if C is not None else None, plan, alpha, beta)
+    rs = A.col_sizes if trans_a else A.row_sizes
+    cs = B.row_sizes if trans_b else B.col_sizes
+    res = BlockSparseMatrix(plan.c_pattern(), out, rs, cs)
+    res.plan = plan
+    return res

@@ -1,0 +1,116 @@
+"""ctypes binding of libbsm.so (the C ABI declared in include/bsm.h).
+
+Argument marshalling only: every function here forwards to the library of
+the same name.  There is no fallback: if the library is missing the import
+of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsm.so")
+
+BSM_OK = 0
+BSM_E_INVALID = -1
+BSM_E_DUPLICATE = -2
+BSM_E_SHAPE = -3
+BSM_E_NOMEM = -4
+BSM_E_DEVICE = -5
+BSM_E_UNSUPPORTED = -6
+
+PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
+
+
+class BsmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libbsm error {code}: {msg}")
+        self.code = code
+
+
+class MmOpts(C.Structure):
+    _fields_ = [("trans_a", C.c_int32), ("trans_b", C.c_int32),
+                ("retain_sparsity", C.c_int32), ("precision", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("c_nblk", C.c_int64), ("c_nvals", C.c_int64), ("nprod", C.c_int64),
+                ("ncand", C.c_int64), ("flops", C.c_int64), ("ntasks", C.c_int64),
+                ("c_nbr", C.c_int32), ("c_nbc", C.c_int32)]
+
+
+_vp = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_dp = C.c_void_p  # device pointers are passed as raw addresses
+
+# name -> argtypes (all return int32 status unless listed in _RESTYPE)
+PROTOTYPES = {
+    "bsm_last_error": [],
+    "bsm_version": [],
+    "bsm_ctx_create": [C.c_int32, _vp, C.POINTER(_vp)],
+    "bsm_ctx_set_stream": [_vp, _vp],
+    "bsm_sync": [_vp],
+    "bsm_ctx_destroy": [_vp],
+    "bsm_pattern_create": [_vp, C.c_int32, _i32p, C.c_int32, _i32p, C.c_int64, _i32p, _i32p,
+                           _i64p, C.POINTER(_vp)],
+    "bsm_pattern_info": [_vp, _i32p, _i32p, _i64p, _i64p],
+    "bsm_pattern_export": [_vp, _i32p, _i32p, _i64p],
+    "bsm_pattern_destroy": [_vp],
+    "bsm_block_norms": [_vp, _vp, _dp, _dp],
+    "bsm_multiply_plan": [_vp, _vp, _dp, _dp, _vp, _dp, _dp, _vp, C.c_double,
+                          C.POINTER(MmOpts), C.POINTER(_vp)],
+    "bsm_plan_info": [_vp, C.POINTER(PlanInfo)],
+    "bsm_plan_c_pattern": [_vp, C.POINTER(_vp)],
+    "bsm_plan_export_stack": [_vp, _i64p, _i64p, _i64p],
+    "bsm_plan_execute": [_vp, C.c_double, _dp, _dp, C.c_double, _dp, _dp],
+    "bsm_multiply": [_vp, C.c_double, _vp, _dp, _vp, _dp, C.c_double, _vp, _dp, _dp, C.c_double,
+                     C.POINTER(MmOpts)],
+    "bsm_plan_backward": [_vp, C.c_double, _dp, _dp, _dp, _dp, _dp],
+    "bsm_plan_destroy": [_vp],
+    "bsm_batch_create": [_vp, C.c_int32, C.POINTER(_vp), C.POINTER(_vp)],
+    "bsm_batch_execute": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_vp),
+                          C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int32],
+    "bsm_batch_destroy": [_vp],
+    "bsm_tpattern_create": [_vp, C.c_int32, _i32p, C.POINTER(_i32p), C.c_int64, _i32p, _i64p,
+                            C.POINTER(_vp)],
+    "bsm_tpattern_info": [_vp, _i32p, _i64p, _i64p],
+    "bsm_tpattern_export": [_vp, _i32p, _i64p],
+    "bsm_tpattern_destroy": [_vp],
+    "bsm_contract_plan": [_vp, C.c_char_p, _vp, _dp, _vp, _dp, _vp, C.c_double,
+                          C.POINTER(MmOpts), C.POINTER(_vp)],
+    "bsm_plan_t3_pattern": [_vp, C.POINTER(_vp)],
+    "bsm_tune_load": [C.c_char_p],
+    "bsm_tune_get": [_i32p],
+    "bsm_tune_set": [_i32p],
+}
+_RESTYPE = {"bsm_last_error": C.c_char_p, "bsm_version": C.c_int32}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_1910_13555_amd/build.py` "
+                          "(or __graft_entry__.build()) first")
+    lib = C.CDLL(LIB_PATH)
+    for name, args in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPE.get(name, C.c_int32)
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int):
+    if status != BSM_OK:
+        raise BsmError(status, lib.bsm_last_error().decode())
+
+
+def as_i32p(a):
+    return a.ctypes.data_as(_i32p) if a is not None else None
+
+
+def as_i64p(a):
+    return a.ctypes.data_as(_i64p) if a is not None else None

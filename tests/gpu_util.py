@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU parity tests (no oracle arithmetic here)."""
+import numpy as np
+import torch
+
+from oracle import blocksparse as ob
+
+
+def to_oracle(pattern, values, row_sizes, col_sizes):
+    """Library result (pattern + device values) as an oracle BlockSparse."""
+    rows, cols, offs = pattern.export()
+    vals = values.detach().cpu().numpy()
+    rs = np.asarray(row_sizes, np.int64)
+    cs = np.asarray(col_sizes, np.int64)
+    blocks = {}
+    for r, c, o in zip(rows.tolist(), cols.tolist(), offs.tolist()):
+        blocks[(r, c)] = vals[o:o + rs[r] * cs[c]].reshape(rs[r], cs[c]).copy()
+    return ob.BlockSparse(rs, cs, blocks)
+
+
+def oracle_from_matrix(M):
+    """Oracle copy of a library BlockSparseMatrix's inputs (values copied back)."""
+    return to_oracle(M.pattern, M.values, M.row_sizes, M.col_sizes)
+
+
+def stack_triples(plan, A, B, trans_a=False, trans_b=False, Cpat=None):
+    """Kept products of a plan as op-space (i,k,j) triples, sorted.
+
+    Also checks the stack's own order: grouped by output block in canonical
+    order, k ascending inside a block."""
+    a, b, c = plan.export_stack()
+    ar, ac, _ = A.pattern.export()
+    br, bc, _ = B.pattern.export()
+    cp = Cpat if Cpat is not None else plan.c_pattern()
+    cr, cc, _ = cp.export()
+    out = []
+    for x, y, z in zip(a.tolist(), b.tolist(), c.tolist()):
+        i, k = (ac[x], ar[x]) if trans_a else (ar[x], ac[x])
+        k2, j = (bc[y], br[y]) if trans_b else (br[y], bc[y])
+        assert k == k2 and i == cr[z] and j == cc[z]
+        out.append((int(i), int(k), int(j)))
+    keyed = [(i, j, k) for i, k, j in out]
+    assert keyed == sorted(keyed), "stack not grouped by output block / ordered by k"
+    return sorted(out)
+
+
+def assert_close(got, ref, tol):
+    assert sorted(got.blocks) == sorted(ref.blocks), "patterns differ"
+    err = ob.rel_frob_diff(got, ref)
+    assert err <= tol, f"relative Frobenius error {err:.3e} > {tol}"
+    return err

@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/bsm.h, and validates / canonicalises block lists on the
+host (host-only context, device -1)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bsm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:bsm_status|const char\*|int32_t)\s+(bsm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1910_13555_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 20
+    raw = C.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), f"{n} declared in bsm.h but not exported"
+    assert set(names) == set(_lib.PROTOTYPES), "binding and header disagree"
+
+
+def _host_ctx():
+    from paper_1910_13555_amd import _lib
+    h = C.c_void_p()
+    _lib.check(_lib.lib.bsm_ctx_create(-1, None, C.byref(h)))
+    return h
+
+
+def _create(ctx, rs, cs, rows, cols):
+    from paper_1910_13555_amd import _lib
+    rs = np.asarray(rs, np.int32); cs = np.asarray(cs, np.int32)
+    r = np.asarray(rows, np.int32); c = np.asarray(cols, np.int32)
+    perm = np.empty(len(r), np.int64)
+    h = C.c_void_p()
+    st = _lib.lib.bsm_pattern_create(ctx, len(rs), _lib.as_i32p(rs), len(cs), _lib.as_i32p(cs), len(r),
+                                     _lib.as_i32p(r), _lib.as_i32p(c), _lib.as_i64p(perm), C.byref(h))
+    return st, h, perm
+
+
+def test_canonicalisation_and_export():
+    from paper_1910_13555_amd import _lib
+    ctx = _host_ctx()
+    rng = np.random.default_rng(0)
+    rs = rng.integers(1, 30, 17); cs = rng.integers(1, 30, 11)
+    slots = rng.choice(17 * 11, 60, replace=False)
+    rows, cols = slots // 11, slots % 11
+    st, h, perm = _create(ctx, rs, cs, rows, cols)
+    assert st == 0
+    order = np.lexsort((cols, rows))
+    assert np.array_equal(perm[order], np.arange(60))
+    nbr, nbc, nblk, nvals = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+    _lib.check(_lib.lib.bsm_pattern_info(h, C.byref(nbr), C.byref(nbc), C.byref(nblk), C.byref(nvals)))
+    lens = rs[rows[order]].astype(np.int64) * cs[cols[order]]
+    assert (nbr.value, nbc.value, nblk.value, nvals.value) == (17, 11, 60, int(lens.sum()))
+    er = np.empty(60, np.int32); ec = np.empty(60, np.int32); eo = np.empty(60, np.int64)
+    _lib.check(_lib.lib.bsm_pattern_export(h, _lib.as_i32p(er), _lib.as_i32p(ec), _lib.as_i64p(eo)))
+    assert np.array_equal(er, rows[order]) and np.array_equal(ec, cols[order])
+    assert np.array_equal(eo, np.concatenate([[0], np.cumsum(lens)[:-1]]))
+    _lib.check(_lib.lib.bsm_pattern_destroy(h))
+    _lib.check(_lib.lib.bsm_pattern_destroy(None))
+    _lib.check(_lib.lib.bsm_ctx_destroy(ctx))
+
+
+@pytest.mark.parametrize("case,code", [
+    ("duplicate", -2), ("row_out_of_range", -1), ("col_negative", -1),
+    ("zero_size", -1), ("huge_size", -1)])
+def test_validation_status_codes(case, code):
+    from paper_1910_13555_amd import _lib
+    ctx = _host_ctx()
+    rs, cs, rows, cols = [2, 3], [4, 5], [0, 1], [1, 0]
+    if case == "duplicate":
+        rows, cols = [0, 1, 0], [1, 0, 1]
+    elif case == "row_out_of_range":
+        rows = [0, 2]
+    elif case == "col_negative":
+        cols = [-1, 0]
+    elif case == "zero_size":
+        rs = [0, 3]
+    elif case == "huge_size":
+        cs = [4, 70000]
+    st, h, _ = _create(ctx, rs, cs, rows, cols)
+    assert st == code
+    assert h.value is None
+    assert len(_lib.lib.bsm_last_error()) > 0
+    _lib.check(_lib.lib.bsm_ctx_destroy(ctx))
+
+
+def test_device_calls_on_host_context_fail_cleanly():
+    from paper_1910_13555_amd import _lib
+    ctx = _host_ctx()
+    st, A, _ = _create(ctx, [2], [2], [0], [0])
+    assert st == 0
+    plan = C.c_void_p()
+    o = _lib.MmOpts(0, 0, 0, 0)
+    st = _lib.lib.bsm_multiply_plan(ctx, A, None, None, A, None, None, None, 0.0, C.byref(o), C.byref(plan))
+    assert st == _lib.BSM_E_DEVICE
+    st = _lib.lib.bsm_multiply_plan(ctx, A, None, None, A, None, None, None, -1.0, C.byref(o), C.byref(plan))
+    assert st == _lib.BSM_E_INVALID
+    st2, B, _ = _create(ctx, [3], [2], [0], [0])
+    st = _lib.lib.bsm_multiply_plan(ctx, A, None, None, B, None, None, None, 0.0, C.byref(o), C.byref(plan))
+    assert st == _lib.BSM_E_SHAPE
+    for h in (A, B):
+        _lib.check(_lib.lib.bsm_pattern_destroy(h))
+    _lib.check(_lib.lib.bsm_ctx_destroy(ctx))

@@ -1,0 +1,149 @@
+"""GPU parity of the block-sparse multiply against the CPU oracle.
+
+Patterns and stacks must match bit for bit; values within relative
+Frobenius error 1e-12 (float64)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import blocksparse as ob
+from gpu_util import assert_close, oracle_from_matrix, stack_triples, to_oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def bsm():
+    import paper_1910_13555_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def run(bsm, dA, dB, dC=None, alpha=1.0, beta=0.0, eps=0.0, ta=False, tb=False, rs=False):
+    A = bsm.BlockSparseMatrix.from_workload(dA)
+    B = bsm.BlockSparseMatrix.from_workload(dB)
+    Cm = bsm.BlockSparseMatrix.from_workload(dC) if dC is not None else None
+    out = bsm.matmul(A, B, Cm, alpha, beta, eps, ta, tb, rs)
+    torch.cuda.synchronize()
+    return A, B, Cm, out
+
+
+def check_against_oracle(bsm, dA, dB, dC=None, alpha=1.0, beta=0.0, eps=0.0, ta=False, tb=False,
+                         rs=False):
+    A, B, Cm, out = run(bsm, dA, dB, dC, alpha, beta, eps, ta, tb, rs)
+    oA, oB = ob.BlockSparse.from_workload(dA), ob.BlockSparse.from_workload(dB)
+    oC = ob.BlockSparse.from_workload(dC) if dC is not None else None
+    ref, trip = ob.multiply(oA, oB, oC, alpha, beta, eps, ta, tb, rs)
+    got = to_oracle(out.pattern, out.values, ref.row_sizes, ref.col_sizes)
+    assert stack_triples(out.plan, A, B, ta, tb, out.pattern) == sorted(trip)
+    assert out.plan.info["flops"] == ob.flop_count(oA, oB, trip, ta, tb)
+    if ref.blocks:
+        assert_close(got, ref, TOL)
+    return out
+
+
+def test_small_uniform(bsm):
+    d = workloads.small_uniform()
+    check_against_oracle(bsm, d["A"], d["B"])
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_cases(bsm, seed):
+    rng = np.random.default_rng(1000 + seed)
+    sizes = [(1, 2, 3, 4), (5, 13, 23), (1, 8, 33, 47), (31, 32, 33)][seed % 4]
+    nbr, nbk, nbc = (int(x) for x in rng.integers(1, 9, 3))
+    dA, dB, dC = workloads.random_case(rng, nbr, nbk, nbc, sizes, 0.5, 0.5,
+                                       0.3 if seed % 3 == 0 else 0.0)
+    ta, tb = bool(seed % 2), bool((seed // 2) % 2)
+    if ta:
+        dA = workloads.random_matrix(rng, dA["col_sizes"], dA["row_sizes"], 0.5)
+    if tb:
+        dB = workloads.random_matrix(rng, dB["col_sizes"], dB["row_sizes"], 0.5)
+    alpha = [1.0, -0.5, 2.0][seed % 3]
+    beta = [0.0, 1.0, 0.25][(seed // 3) % 3] if dC is not None else 0.0
+    eps = 0.0
+    if seed % 5 == 1:
+        oA, oB = ob.BlockSparse.from_workload(dA), ob.BlockSparse.from_workload(dB)
+        na = sorted(ob.norms(oA).values())
+        nb = sorted(ob.norms(oB).values())
+        if na and nb:
+            eps = math.sqrt(na[len(na) // 2] * nb[len(nb) // 2])
+    rs = seed % 7 == 0 and dC is not None
+    check_against_oracle(bsm, dA, dB, dC, alpha, beta, eps, ta, tb, rs)
+
+
+def test_empty_and_degenerate(bsm):
+    rng = np.random.default_rng(5)
+    sizes = np.array([3, 4], np.int32)
+    empty = workloads.make_matrix(sizes, sizes, [], [], np.zeros(0))
+    full = workloads.random_matrix(rng, sizes, sizes, 1.0)
+    check_against_oracle(bsm, empty, full)
+    check_against_oracle(bsm, full, empty)
+    # eps = inf keeps nothing: C_out = beta * C_in
+    C = workloads.random_matrix(rng, sizes, sizes, 0.5)
+    out = check_against_oracle(bsm, full, full, C, 1.0, -2.0, 1e300)
+    assert out.plan.info["nprod"] == 0
+
+
+def test_deterministic_and_inplace(bsm):
+    d = workloads.banded(nblk=120, seed_tag=7)
+    A = bsm.BlockSparseMatrix.from_workload(d["A"])
+    B = bsm.BlockSparseMatrix.from_workload(d["B"])
+    r1 = bsm.matmul(A, B, filter_eps=d["eps"]).values.clone()
+    r2 = bsm.matmul(A, B, filter_eps=d["eps"]).values.clone()
+    assert torch.equal(r1, r2)
+    # in place: C = C + A.B where C already holds the product pattern
+    Cm = bsm.matmul(A, B, filter_eps=d["eps"])
+    plan = bsm.bsm_multiply_plan(A.pattern.ctx, A.pattern, A.values, B.pattern, B.values,
+                                 Cm.pattern, d["eps"])
+    before = Cm.values.clone()
+    plan.execute(1.0, A.values, B.values, 1.0, Cm.values, Cm.values)
+    torch.cuda.synchronize()
+    torch.testing.assert_close(Cm.values, 2 * before, rtol=1e-13, atol=1e-13)
+
+
+def test_banded_small_full_oracle(bsm):
+    d = workloads.banded(nblk=300, seed_tag=8)
+    check_against_oracle(bsm, d["A"], d["B"], eps=d["eps"])
+
+
+def test_tall_skinny_small_full_oracle(bsm):
+    d = workloads.tall_skinny(nrow=40, nk=20000, seed_tag=9)
+    check_against_oracle(bsm, d["A"], d["B"], d["C"], d["alpha"], d["beta"])
+
+
+def sampled_rows_check(bsm, d, nsample, seed):
+    A = bsm.BlockSparseMatrix.from_workload(d["A"])
+    B = bsm.BlockSparseMatrix.from_workload(d["B"])
+    Cm = bsm.BlockSparseMatrix.from_workload(d["C"]) if d["C"] is not None else None
+    out = bsm.matmul(A, B, Cm, d["alpha"], d["beta"], d["eps"])
+    torch.cuda.synchronize()
+    oA, oB = ob.BlockSparse.from_workload(d["A"]), ob.BlockSparse.from_workload(d["B"])
+    oC = ob.BlockSparse.from_workload(d["C"]) if d["C"] is not None else None
+    rng = np.random.default_rng(seed)
+    rows = set(rng.choice(len(d["A"]["row_sizes"]), nsample, replace=False).tolist())
+    ref, trip = ob.multiply(oA, oB, oC, d["alpha"], d["beta"], d["eps"], rows=rows)
+    got_all = to_oracle(out.pattern, out.values, ref.row_sizes, ref.col_sizes)
+    got = ob.BlockSparse(ref.row_sizes, ref.col_sizes,
+                         {k: v for k, v in got_all.blocks.items() if k[0] in rows})
+    err = assert_close(got, ref, TOL)
+    st = [t for t in stack_triples(out.plan, A, B, Cpat=out.pattern) if t[0] in rows]
+    assert st == sorted(trip)
+    return out, err
+
+
+def test_banded_full_size_sampled_rows(bsm):
+    d = workloads.banded()
+    out, err = sampled_rows_check(bsm, d, 12, 0)
+    info = out.plan.info
+    assert info["ncand"] > info["nprod"], "the norm filter should drop some products here"
+    print(f"banded: {info['nprod']} products, {info['c_nblk']} blocks, {info['flops']/1e9:.2f} GF, err {err:.2e}")
+
+
+def test_tall_skinny_full_size_sampled_rows(bsm):
+    d = workloads.tall_skinny()
+    sampled_rows_check(bsm, d, 10, 1)
