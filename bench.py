@@ -1,0 +1,178 @@
+"""Benchmark: useful FP64 GFLOP/s of the filtered block-sparse multiply.
+
+One step = one full multiply C = A.B of the banded workload (2000 x 2000
+blocks of sizes {5,13,23}, band probability 0.5*exp(-|i-j|/40), values
+N(0,1)*exp(-|i-j|/20), filter eps 1e-8): block norms, symbolic phase with the
+single size readback, and the numeric kernel.  Inputs are resident in HBM
+before timing starts.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B; % FP64 roofline; split vs FP64"
+PEAK_FP64 = 78.6e12       # MI355X dense FP64 (vector and matrix core), FLOP/s
+PEAK_HBM = 8.0e12         # MI355X HBM3E, B/s
+KERNELS_SRC = os.path.join(ROOT, "paper_1910_13555_amd", "csrc", "bsm_numeric.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_traffic_banded.json")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNELS_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per numeric launch from the committed rocprofv3 counter runs,
+    or None if the kernel source changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def compulsory_bytes(plan, A, B, beta):
+    """Touched A and B blocks read once, C_out written once (C_in read if beta != 0)."""
+    import numpy as np
+    a, b, _ = plan.export_stack()
+    _, _, aoff = A.pattern.export()
+    _, _, boff = B.pattern.export()
+    alen = np.diff(np.append(aoff, A.pattern.nvals))
+    blen = np.diff(np.append(boff, B.pattern.nvals))
+    by = 8 * (int(alen[np.unique(a)].sum()) + int(blen[np.unique(b)].sum()) + plan.info["c_nvals"])
+    return by
+
+
+def cpu_baseline(d, nrows=500):
+    """The CPU oracle timed on a bounded sample: every 4th output block row."""
+    from threadpoolctl import threadpool_limits
+    from oracle import blocksparse as ob
+    A = ob.BlockSparse.from_workload(d["A"])
+    B = ob.BlockSparse.from_workload(d["B"])
+    n = len(d["A"]["row_sizes"])
+    rows = set(range(0, n, max(1, n // nrows)))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        _, trip = ob.multiply(A, B, eps=d["eps"], rows=rows)
+        dt = time.perf_counter() - t0
+    f = ob.flop_count(A, B, trip)
+    return {"value": f / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(rows)} of {n} output block rows of the same workload "
+                      f"({len(trip)} products, {f / 1e9:.3f} GFLOP), block-loop oracle, "
+                      f"1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1910_13555_amd as bsm
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    d = workloads.banded()
+    A = bsm.BlockSparseMatrix.from_workload(d["A"])
+    B = bsm.BlockSparseMatrix.from_workload(d["B"])
+    ctx = A.pattern.ctx
+    eps = d["eps"]
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, None, eps)
+        out = torch.empty(plan.info["c_nvals"], dtype=torch.float64, device=dev)
+        if ev is not None:
+            ev[0].record(stream)
+        plan.execute(1.0, A.values, B.values, 0.0, None, out)
+        if ev is not None:
+            ev[1].record(stream)
+        return plan, out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    plans = []
+    for k in range(args.steps):
+        plan, out = step(evs[k])
+        plans.append(plan)  # keep alive until the clock stops (destroy is host work)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    numeric_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
+    plan = plans[-1]
+    info = plan.info
+    plans = plans[:1]
+
+    # numeric-only rate (plan reuse, as in repeated multiplies with a fixed pattern)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(1.0, A.values, B.values, 0.0, None, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    reuse_ms = e0.elapsed_time(e1) / args.steps
+
+    F = info["flops"]
+    Bytes = compulsory_bytes(plan, A, B, 0.0)
+    t_roof = max(F / PEAK_FP64, Bytes / PEAK_HBM)
+    achieved = F / (numeric_ms * 1e-3)
+    res = {
+        "metric": METRIC,
+        "value": F / (ms_step * 1e-3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": d["name"], "block_rows": 2000, "block_sizes": [5, 13, 23],
+                   "pattern": "P(i,j)=0.5*exp(-|i-j|/40)", "filter_eps": eps,
+                   "products": info["nprod"], "candidates": info["ncand"],
+                   "c_blocks": info["c_nblk"], "useful_gflop": F / 1e9,
+                   "compulsory_bytes": Bytes},
+        "pct_fp64_roofline": 100.0 * t_roof * 1e3 / ms_step,
+        "t_roof_ms": t_roof * 1e3,
+        "numeric_ms": numeric_ms,
+        "numeric_only_gflops": F / (reuse_ms * 1e-3) / 1e9,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                     "traffic": recorded_traffic(),
+                     "kernel": "k_numeric (FP64 4x4x4 matrix-core tiles, all classes, one launch)"},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(d)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,11 +180,15 @@ bsm_status bsm_multiply(bsm_ctx ctx, double alpha, bsm_pattern A, const double* 
  *          d op(B)_kj = alpha * sum_i op(A)_ik^T . dC_ij   on pat(B).
  * dc_vals: device, pat(C_out) layout.  da_vals / db_vals: device outputs in
  * the stored layout of A / B, overwritten (blocks without products get 0);
- * either may be NULL to skip it.  dC_in = beta*dC is left to the caller.
- * The first call builds the regrouped product lists and keeps them. */
+ * either may be NULL to skip it.  The first call builds, per operand, one
+ * product list per block of that operand (same norm test, same output
+ * pattern) and keeps them with the plan.  FP64 plans only. */
 bsm_status bsm_plan_backward(bsm_plan plan, double alpha, const double* dc_vals,
                              const double* a_vals, const double* b_vals, double* da_vals,
                              double* db_vals);
+/* dC_in = beta * dC on pat(C_in) (device pointers; dcin_vals holds C_in's
+ * values layout).  No-op without C_in. */
+bsm_status bsm_plan_cin_grad(bsm_plan plan, double beta, const double* dc_vals, double* dcin_vals);
 bsm_status bsm_plan_destroy(bsm_plan plan);
 
 /* ------------------------------------------------------------ batches

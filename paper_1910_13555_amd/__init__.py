@@ -215,6 +215,14 @@ class Plan:
                                     _ptr(da), _ptr(db)))
         return da, db
 
+    def cin_grad(self, dc, beta):
+        """dC_in = beta * dC on pat(C_in)."""
+        Cp = self._refs[2]
+        out = torch.empty(Cp.nvals, dtype=torch.float64, device=dc.device)
+        self._check_sizes(None, None, None, dc)
+        check(lib.bsm_plan_cin_grad(self.handle, float(beta), _ptr(dc), _ptr(out)))
+        return out
+
     def close(self):
         if self.handle:
             check(lib.bsm_plan_destroy(self.handle))
@@ -325,6 +333,110 @@ class _MatmulFn(torch.autograd.Function):
         if ctx_.has_c and ctx_.needs_input_grad[2]:
             dc = ctx_.plan.cin_grad(g, ctx_.beta)
         return da, db, dc, None, None, None
+
+
+class TensorPattern:
+    """Block pattern of a rank 2..4 tensor (Sec. 4); blocks packed in the
+    order export() returns (lexicographic for tensors created here)."""
+
+    def __init__(self, ctx: Context, handle, mode_sizes):
+        self.ctx, self.handle = ctx, handle
+        self.mode_sizes = [np.asarray(s, np.int32) for s in mode_sizes]
+        _live["pattern"].add(self)
+        rank, nblocks, nvals = C.c_int32(), C.c_int64(), C.c_int64()
+        check(lib.bsm_tpattern_info(handle, C.byref(rank), C.byref(nblocks), C.byref(nvals)))
+        self.rank, self.nblocks, self.nvals = rank.value, nblocks.value, nvals.value
+
+    def export(self):
+        idx = np.empty((self.nblocks, self.rank), np.int32)
+        offs = np.empty(self.nblocks, np.int64)
+        check(lib.bsm_tpattern_export(self.handle, _lib.as_i32p(idx), _lib.as_i64p(offs)))
+        return idx, offs
+
+    def close(self):
+        if self.handle:
+            check(lib.bsm_tpattern_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bsm_tpattern_create(ctx: Context, mode_sizes, idx):
+    """Returns (TensorPattern, perm) with perm[l] = packing slot of input block l."""
+    sizes = [np.ascontiguousarray(s, np.int32) for s in mode_sizes]
+    rank = len(sizes)
+    ix = np.ascontiguousarray(idx, np.int32).reshape(-1, rank)
+    nb = np.array([len(s) for s in sizes], np.int32)
+    arr = (_lib._i32p * rank)(*[_lib.as_i32p(s) for s in sizes])
+    perm = np.empty(len(ix), np.int64)
+    h = C.c_void_p()
+    check(lib.bsm_tpattern_create(ctx.handle, rank, _lib.as_i32p(nb), arr, len(ix), _lib.as_i32p(ix),
+                                  _lib.as_i64p(perm), C.byref(h)))
+    return TensorPattern(ctx, h, sizes), perm
+
+
+class ContractPlan(Plan):
+    def t3_pattern(self, mode_sizes) -> TensorPattern:
+        h = C.c_void_p()
+        check(lib.bsm_plan_t3_pattern(self.handle, C.byref(h)))
+        return TensorPattern(self.ctx, h, mode_sizes)
+
+
+def bsm_contract_plan(ctx: Context, spec: str, T1: TensorPattern, t1_vals, T2: TensorPattern, t2_vals,
+                      T3_in: TensorPattern = None, filter_eps: float = 0.0,
+                      retain_sparsity=False) -> ContractPlan:
+    h = C.c_void_p()
+    o = _opts(False, False, retain_sparsity)
+    check(lib.bsm_contract_plan(ctx.handle, spec.encode(), T1.handle, _ptr(t1_vals), T2.handle,
+                                _ptr(t2_vals), T3_in.handle if T3_in else None, float(filter_eps),
+                                C.byref(o), C.byref(h)))
+    return ContractPlan(ctx, h, (T1, T2, T3_in))
+
+
+class BlockSparseTensor:
+    """Tensor pattern plus float64 values in the pattern's packing order."""
+
+    def __init__(self, pattern: TensorPattern, values: torch.Tensor):
+        if values.numel() != pattern.nvals:
+            raise ValueError(f"{values.numel()} values for a pattern of {pattern.nvals}")
+        self.pattern, self.values = pattern, values
+
+    @property
+    def mode_sizes(self):
+        return self.pattern.mode_sizes
+
+    @classmethod
+    def from_lists(cls, mode_sizes, idx, values, device=0, ctx=None):
+        """Blocks in lexicographic order of ``idx`` (as the generators give
+        them); ``values`` holds them one after another, row-major each."""
+        ctx = ctx or default_context(device)
+        pat, perm = bsm_tpattern_create(ctx, mode_sizes, idx)
+        if not np.array_equal(perm, np.arange(len(perm))):
+            raise ValueError("tensor blocks must be listed in lexicographic order")
+        if isinstance(values, torch.Tensor):
+            vals = values.to(device=f"cuda:{device}", dtype=torch.float64).contiguous()
+        else:
+            vals = torch.from_numpy(np.ascontiguousarray(values, np.float64)).to(f"cuda:{device}")
+        return cls(pat, vals)
+
+
+def contract(spec: str, T1: BlockSparseTensor, T2: BlockSparseTensor, T3: BlockSparseTensor = None,
+             alpha=1.0, beta=0.0, filter_eps=0.0) -> BlockSparseTensor:
+    """Block-sparse tensor contraction (Sec. 4), differentiable in T1, T2, T3."""
+    ctx = T1.pattern.ctx
+    plan = bsm_contract_plan(ctx, spec, T1.pattern, T1.values, T2.pattern, T2.values,
+                             T3.pattern if T3 is not None else None, filter_eps)
+    out = _MatmulFn.apply(T1.values, T2.values, T3.values if T3 is not None else None, plan, alpha, beta)
+    lhs, o = spec.replace(" ", "").split("->")
+    s1, s2 = lhs.split(",")
+    sizes = [T1.mode_sizes[s1.index(c)] if c in s1 else T2.mode_sizes[s2.index(c)] for c in o]
+    res = BlockSparseTensor(plan.t3_pattern(sizes), out)
+    res.plan = plan
+    return res
 
 
 def matmul(A: BlockSparseMatrix, B: BlockSparseMatrix, C: BlockSparseMatrix = None, alpha=1.0,

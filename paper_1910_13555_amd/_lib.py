@@ -68,6 +68,7 @@ PROTOTYPES = {
     "bsm_multiply": [_vp, C.c_double, _vp, _dp, _vp, _dp, C.c_double, _vp, _dp, _dp, C.c_double,
                      C.POINTER(MmOpts)],
     "bsm_plan_backward": [_vp, C.c_double, _dp, _dp, _dp, _dp, _dp],
+    "bsm_plan_cin_grad": [_vp, C.c_double, _dp, _dp],
     "bsm_plan_destroy": [_vp],
     "bsm_batch_create": [_vp, C.c_int32, C.POINTER(_vp), C.POINTER(_vp)],
     "bsm_batch_execute": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_vp),

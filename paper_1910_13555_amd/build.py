@@ -1,7 +1,8 @@
 """Build libbsm.so for gfx950 in-tree with hipcc (no JIT, no torch extension).
 
-Sources: csrc/bsm_kernels.hip (device kernels and launchers) and
-csrc/bsm_api.cpp (host planner and the C ABI of include/bsm.h).
+Sources: csrc/bsm_symbolic.hip (norms, symbolic phase), csrc/bsm_numeric.hip
+(numeric kernel), csrc/bsm_backward.hip (gradient product lists) and csrc/bsm_api.cpp (host
+planner and the C ABI of include/bsm.h).
 """
 from __future__ import annotations
 
@@ -24,7 +25,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result",
          "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["bsm_kernels.hip", "bsm_api.cpp"]
+SOURCES = ["bsm_symbolic.hip", "bsm_numeric.hip", "bsm_backward.hip", "bsm_remap.hip",
+           "bsm_api.cpp", "bsm_tensor.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -1,370 +1,25 @@
-// Host side of libbsm: the C ABI declared in include/bsm.h.
+// Host side of libbsm for matrices: the C ABI declared in include/bsm.h
+// (tensors live in bsm_tensor.cpp).
 //
 // Validation and canonicalisation of block lists (Sec. 2's blocked CSR index)
 // run on the host; everything that touches values or grows with the number
-// of products runs on the device (bsm_kernels.hip).  Index memory comes from
-// a per-context caching allocator; all device work is queued on the
-// context's stream, so memory returned to the cache can be reused by later
-// work on the same stream without waiting.
-#include <hip/hip_runtime.h>
+// of products runs on the device (bsm_symbolic.hip, bsm_numeric.hip,
+// bsm_backward.hip).  Index memory comes from a per-context caching
+// allocator; all device work is queued on the context's stream, so memory
+// returned to the cache can be reused by later work on the same stream
+// without waiting.
+#include "bsm_host.h"
 
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <map>
-#include <memory>
-#include <numeric>
-#include <stdexcept>
-#include <string>
-#include <vector>
+namespace bsm_host {
 
-#include "../../include/bsm.h"
-#include "bsm_internal.h"
-
-using namespace bsm;
-
-namespace {
-
-thread_local std::string g_err;
-
-struct Error : std::runtime_error {
-  bsm_status code;
-  Error(bsm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
-
-[[noreturn]] void fail(bsm_status c, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  throw Error(c, buf);
-}
-
-void hip_check(hipError_t e, const char* what) {
-  if (e == hipSuccess) return;
-  if (e == hipErrorOutOfMemory) fail(BSM_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
-  fail(BSM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-template <class F>
-bsm_status guard(F&& f) {
-  try {
-    f();
-    return BSM_OK;
-  } catch (const Error& e) {
-    g_err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return BSM_E_NOMEM;
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return BSM_E_INVALID;
-  }
-}
-
-// ------------------------------------------------------------ allocator
-
-// Size-bucketed cache of device allocations.  Blocks go back to the cache
-// when their owner is destroyed; because all work of a context is ordered on
-// its stream, a cached block can be handed out again at once.
-struct Allocator {
-  int device = 0;
-  std::multimap<size_t, void*> free_;
-  std::map<void*, size_t> live_;
-  size_t cached_bytes = 0;
-
-  static size_t round(size_t n) { return (n + 511) & ~size_t(511); }
-
-  void* alloc(size_t n) {
-    if (n == 0) n = 1;
-    n = round(n);
-    auto it = free_.lower_bound(n);
-    if (it != free_.end() && it->first <= 2 * n) {
-      void* p = it->second;
-      live_[p] = it->first;
-      cached_bytes -= it->first;
-      free_.erase(it);
-      return p;
-    }
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      release_cache();
-      e = hipMalloc(&p, n);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(BSM_E_NOMEM, "device allocation of %zu bytes failed", n);
-      }
-    }
-    live_[p] = n;
-    return p;
-  }
-  void free(void* p) {
-    if (!p) return;
-    auto it = live_.find(p);
-    if (it == live_.end()) return;
-    free_.emplace(it->second, p);
-    cached_bytes += it->second;
-    live_.erase(it);
-  }
-  void release_cache() {
-    for (auto& kv : free_) (void)hipFree(kv.second);
-    free_.clear();
-    cached_bytes = 0;
-  }
-  ~Allocator() {
-    release_cache();
-    for (auto& kv : live_) (void)hipFree(kv.first);
-  }
-};
-
-}  // namespace
-
-struct bsm_ctx_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int refs = 1;  // the creator's reference plus one per live pattern / plan / batch
-  Allocator mem;
-};
-
-namespace {
-
-// Contexts are freed when the last object using their allocator goes away,
-// whatever order the caller destroys handles in.
-void ctx_release(bsm_ctx c) {
-  if (!c || --c->refs > 0) return;
-  if (c->device >= 0) {
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-  }
-  delete c;
-}
-
-struct CtxRef {
-  bsm_ctx c = nullptr;
-  CtxRef() = default;
-  CtxRef(const CtxRef&) = delete;
-  CtxRef& operator=(const CtxRef&) = delete;
-  CtxRef& operator=(bsm_ctx x) {
-    if (x) x->refs++;
-    ctx_release(c);
-    c = x;
-    return *this;
-  }
-  ~CtxRef() { ctx_release(c); }
-  operator bsm_ctx() const { return c; }
-  bsm_ctx operator->() const { return c; }
-};
-
-}  // namespace
-
-namespace {
-
-// Device buffer owned by a context's allocator.
-template <class T>
-struct DBuf {
-  bsm_ctx ctx = nullptr;
-  T* p = nullptr;
-  size_t n = 0;
-  DBuf() = default;
-  DBuf(bsm_ctx c, size_t count) : ctx(c), n(count) {
-    p = static_cast<T*>(c->mem.alloc(sizeof(T) * std::max<size_t>(count, 1)));
-  }
-  DBuf(const DBuf&) = delete;
-  DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
-  DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) {
-      reset();
-      ctx = o.ctx; p = o.p; n = o.n;
-      o.p = nullptr; o.n = 0;
-    }
-    return *this;
-  }
-  ~DBuf() { reset(); }
-  void reset() {
-    if (p && ctx) ctx->mem.free(p);
-    p = nullptr;
-    n = 0;
-  }
-  void upload(const T* h, size_t count) {
-    if (count) hip_check(hipMemcpyAsync(p, h, sizeof(T) * count, hipMemcpyHostToDevice, ctx->stream),
-                         "upload");
-  }
-};
-
-template <class T>
-DBuf<T> make_dev(bsm_ctx c, const std::vector<T>& h) {
-  DBuf<T> d(c, h.size());
-  d.upload(h.data(), h.size());
-  return d;
-}
-
-template <class T>
-std::vector<T> download(bsm_ctx c, const T* d, size_t n) {
-  std::vector<T> h(n);
-  if (n) {
-    hip_check(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, c->stream), "download");
-    hip_check(hipStreamSynchronize(c->stream), "download sync");
-  }
-  return h;
-}
-
-void set_device(bsm_ctx c) {
-  if (c->device < 0) fail(BSM_E_DEVICE, "host-only context (device -1) cannot run device work");
-  hip_check(hipSetDevice(c->device), "hipSetDevice");
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------ pattern
-
-struct bsm_pattern_s {
-  CtxRef ctx;  // first member: released after every buffer below
-  int32_t nbr = 0, nbc = 0;
-  int64_t nblk = 0, nvals = 0;
-  // host index (canonical order); filled lazily for device-born patterns
-  bool host_valid = false;
-  std::vector<int32_t> h_rs, h_cs, h_ptr, h_col, h_row;
-  std::vector<int64_t> h_off;  // nblk + 1
-  // device index
-  DBuf<int32_t> d_rs, d_cs, d_ptr, d_col, d_row;
-  DBuf<int64_t> d_off;
-  // transposed index (CSC), built on demand
-  bool t_valid = false;
-  DBuf<int32_t> d_tptr, d_trow, d_tblk;
-
-  void ensure_host() {
-    if (host_valid) return;
-    h_rs = download(ctx, d_rs.p, nbr);
-    h_cs = download(ctx, d_cs.p, nbc);
-    h_ptr = download(ctx, d_ptr.p, nbr + 1);
-    h_col = download(ctx, d_col.p, nblk);
-    h_row = download(ctx, d_row.p, nblk);
-    h_off = download(ctx, d_off.p, nblk + 1);
-    host_valid = true;
-  }
-  void ensure_transpose() {
-    if (t_valid) return;
-    ensure_host();
-    std::vector<int32_t> tptr(nbc + 1, 0), trow(nblk), tblk(nblk);
-    for (int64_t b = 0; b < nblk; ++b) tptr[h_col[b] + 1]++;
-    for (int32_t j = 0; j < nbc; ++j) tptr[j + 1] += tptr[j];
-    std::vector<int32_t> cur(tptr.begin(), tptr.end() - 1);
-    for (int64_t b = 0; b < nblk; ++b) {  // canonical order => rows ascending per column
-      const int32_t q = cur[h_col[b]]++;
-      trow[q] = h_row[b];
-      tblk[q] = (int32_t)b;
-    }
-    d_tptr = make_dev(ctx, tptr);
-    d_trow = make_dev(ctx, trow);
-    d_tblk = make_dev(ctx, tblk);
-    t_valid = true;
-  }
-};
-
-namespace {
-
-void check_sizes(int32_t n, const int32_t* s, const char* what) {
-  if (n < 0) fail(BSM_E_INVALID, "%s: negative block count", what);
-  if (n > 0 && !s) fail(BSM_E_INVALID, "%s: NULL size array", what);
-  for (int32_t i = 0; i < n; ++i)
-    if (s[i] < 1 || s[i] > 65535) fail(BSM_E_INVALID, "%s: block size %d at %d out of [1,65535]", what, s[i], i);
-}
-
-// Canonicalise a block list: sort by (row, col), detect duplicates, offsets.
-bsm_pattern make_pattern(bsm_ctx ctx, int32_t nbr, const int32_t* rs, int32_t nbc, const int32_t* cs,
-                         int64_t nblk, const int32_t* br, const int32_t* bc, int64_t* perm_out) {
-  check_sizes(nbr, rs, "row sizes");
-  check_sizes(nbc, cs, "column sizes");
-  if (nblk < 0) fail(BSM_E_INVALID, "negative block count");
-  if (nblk >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 blocks");
-  if (nblk > 0 && (!br || !bc)) fail(BSM_E_INVALID, "NULL block list");
-  for (int64_t l = 0; l < nblk; ++l)
-    if (br[l] < 0 || br[l] >= nbr || bc[l] < 0 || bc[l] >= nbc)
-      fail(BSM_E_INVALID, "block %lld (%d,%d) out of range", (long long)l, br[l], bc[l]);
-  std::vector<int64_t> order(nblk);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-    return br[x] != br[y] ? br[x] < br[y] : (bc[x] != bc[y] ? bc[x] < bc[y] : x < y);
-  });
-  for (int64_t q = 1; q < nblk; ++q)
-    if (br[order[q]] == br[order[q - 1]] && bc[order[q]] == bc[order[q - 1]])
-      fail(BSM_E_DUPLICATE, "duplicate block (%d,%d)", br[order[q]], bc[order[q]]);
-  auto p = std::make_unique<bsm_pattern_s>();
-  p->ctx = ctx;
-  p->nbr = nbr;
-  p->nbc = nbc;
-  p->nblk = nblk;
-  p->h_rs.assign(rs, rs + nbr);
-  p->h_cs.assign(cs, cs + nbc);
-  p->h_ptr.assign(nbr + 1, 0);
-  p->h_col.resize(nblk);
-  p->h_row.resize(nblk);
-  p->h_off.resize(nblk + 1);
-  int64_t off = 0;
-  for (int64_t q = 0; q < nblk; ++q) {
-    const int64_t l = order[q];
-    p->h_row[q] = br[l];
-    p->h_col[q] = bc[l];
-    p->h_ptr[br[l] + 1]++;
-    p->h_off[q] = off;
-    off += (int64_t)rs[br[l]] * cs[bc[l]];
-    if (perm_out) perm_out[l] = q;
-  }
-  p->h_off[nblk] = off;
-  if (off >= (int64_t(1) << 48)) fail(BSM_E_UNSUPPORTED, "more than 2^48 values");
-  for (int32_t i = 0; i < nbr; ++i) p->h_ptr[i + 1] += p->h_ptr[i];
-  p->nvals = off;
-  p->host_valid = true;
-  if (ctx->device < 0) return p.release();  // host-only context: index only
-  set_device(ctx);
-  p->d_rs = make_dev(ctx, p->h_rs);
-  p->d_cs = make_dev(ctx, p->h_cs);
-  p->d_ptr = make_dev(ctx, p->h_ptr);
-  p->d_col = make_dev(ctx, p->h_col);
-  p->d_row = make_dev(ctx, p->h_row);
-  p->d_off = make_dev(ctx, p->h_off);
-  return p.release();
-}
-
-}  // namespace
-
-// --------------------------------------------------------------------- plan
-
-struct bsm_plan_s {
-  CtxRef ctx;  // first member: released after every buffer below
-  bsm_pattern A = nullptr, B = nullptr, Cin = nullptr;
-  bsm_mm_opts opts{};
-  double eps = 0.0;
-  int32_t nr = 0, nk = 0, nc = 0;
-  int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
-  // output pattern (C_out), device-born
-  int64_t c_nblk = 0, c_nvals = 0, nprod = 0, ncand = 0, flops = 0;
-  bool c_same_as_cin = false;
-  DBuf<int32_t> c_ptr, c_row, c_col, c_rs, c_cs;
-  DBuf<int64_t> c_off, cin_off, pptr, px, py;
-  DBuf<int2> tasks;
-  int32_t cls_cnt[kClasses] = {0};
-  int32_t cls_base[kClasses] = {0};
-  int64_t ntasks = 0;
-  DBuf<int32_t> rowq;  // split factors for tensor layouts (optional)
-};
-
-namespace {
-
+extern const bsm_mm_opts kDefaultOpts;
 const bsm_mm_opts kDefaultOpts = {0, 0, 0, BSM_PREC_FP64};
 
 OpCsr op_csr(bsm_pattern P, bool trans) {
   OpCsr o;
   if (!trans) {
     o.nr = P->nbr; o.nc = P->nbc;
-    o.ptr = P->d_ptr.p; o.col = P->d_col.p; o.blk = nullptr;
+    o.ptr = P->d_ptr.p; o.col = P->d_col.p; o.blk = P->h_blk.empty() ? nullptr : P->d_blk.p;
   } else {
     P->ensure_transpose();
     o.nr = P->nbc; o.nc = P->nbr;
@@ -396,77 +51,66 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     P.cin_col = C->d_col.p;
     P.cin_off = C->d_off.p;
   }
-  DBuf<double> na, nb;
-  if (P.eps2 > 0.0) {
-    if (!a_norms) {
-      if (!a_vals) fail(BSM_E_INVALID, "filter_eps > 0 needs A values or norms");
-      na = DBuf<double>(ctx, A->nblk);
-      hip_check(launch_block_norms(st, A->nblk, A->d_off.p, a_vals, na.p), "norms A");
-      a_norms = na.p;
+  if (P.eps2 > 0.0) {  // the plan keeps its own norms: the gradient reuses the same test
+    pl->na = DBuf<double>(ctx, A->nblk);
+    pl->nb = DBuf<double>(ctx, B->nblk);
+    if (a_norms) {
+      if (A->nblk)
+        hip_check(hipMemcpyAsync(pl->na.p, a_norms, sizeof(double) * A->nblk, hipMemcpyDeviceToDevice, st),
+                  "copy norms A");
+    } else {
+      if (!a_vals && A->nblk) fail(BSM_E_INVALID, "filter_eps > 0 needs A values or norms");
+      hip_check(launch_block_norms(st, A->nblk, A->d_off.p, a_vals, pl->na.p), "norms A");
     }
-    if (!b_norms) {
-      if (!b_vals) fail(BSM_E_INVALID, "filter_eps > 0 needs B values or norms");
-      nb = DBuf<double>(ctx, B->nblk);
-      hip_check(launch_block_norms(st, B->nblk, B->d_off.p, b_vals, nb.p), "norms B");
-      b_norms = nb.p;
+    if (b_norms) {
+      if (B->nblk)
+        hip_check(hipMemcpyAsync(pl->nb.p, b_norms, sizeof(double) * B->nblk, hipMemcpyDeviceToDevice, st),
+                  "copy norms B");
+    } else {
+      if (!b_vals && B->nblk) fail(BSM_E_INVALID, "filter_eps > 0 needs B values or norms");
+      hip_check(launch_block_norms(st, B->nblk, B->d_off.p, b_vals, pl->nb.p), "norms B");
     }
-    P.a.nrm = a_norms;
-    P.b.nrm = b_norms;
+    P.a.nrm = pl->na.p;
+    P.b.nrm = pl->nb.p;
   }
   const int32_t nr = pl->nr;
-  DBuf<int32_t> cnt_blk(ctx, nr);
-  DBuf<int64_t> cnt_el(ctx, nr), cnt_prod(ctx, nr), cnt_cand(ctx, nr), cnt_flops(ctx, nr);
-  DBuf<SymTotals> tot(ctx, 1);
-  hip_check(hipMemsetAsync(tot.p, 0, sizeof(SymTotals), st), "memset");
-  hip_check(launch_sym_count(st, P, cnt_blk.p, cnt_el.p, cnt_prod.p, cnt_cand.p, cnt_flops.p, tot.p),
-            "symbolic count");
+  pl->c_rs = P.rs;
+  pl->c_cs = P.cs;
+  DBuf<int64_t> cnt(ctx, (size_t)kSymFields * nr), base(ctx, (size_t)kSymFields * (nr + 1)),
+      tot(ctx, kSymFields);
+  hip_check(launch_sym_count(st, P, cnt.p), "symbolic count");
+  hip_check(launch_scan_fields(st, kSymFields, nr, cnt.p, base.p, tot.p), "symbolic scan");
+  const std::vector<int64_t> h = download(ctx, tot.p, kSymFields);
+  if (h[kFBlk] >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "output has more than 2^31-2 blocks");
+  if (h[kFVals] >= (int64_t(1) << 48)) fail(BSM_E_UNSUPPORTED, "output has more than 2^48 values");
+  if (h[kFTiles] >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 output tiles");
+  pl->c_nblk = h[kFBlk];
+  pl->c_nvals = h[kFVals];
+  pl->nprod = h[kFProd];
+  pl->ncand = h[kFCand];
+  pl->flops = h[kFFlops];
+  pl->ntasks = h[kFTiles];
   pl->c_ptr = DBuf<int32_t>(ctx, nr + 1);
-  DBuf<int64_t> el_base(ctx, nr + 1), prod_base(ctx, nr + 1);
-  hip_check(launch_scan_rows(st, nr, cnt_blk.p, cnt_el.p, cnt_prod.p, cnt_cand.p, cnt_flops.p,
-                             pl->c_ptr.p, el_base.p, prod_base.p, tot.p),
-            "row scan");
-  SymTotals h = download(ctx, tot.p, 1)[0];
-  if (h.nblk >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "output has more than 2^31-2 blocks");
-  if (h.nvals >= (int64_t(1) << 48)) fail(BSM_E_UNSUPPORTED, "output has more than 2^48 values");
-  pl->c_nblk = h.nblk;
-  pl->c_nvals = h.nvals;
-  pl->nprod = h.nprod;
-  pl->ncand = h.ncand;
-  pl->flops = h.flops;
-  pl->ntasks = 0;
-  for (int c = kClasses - 1; c >= 0; --c) {  // largest tile class first
-    pl->cls_cnt[c] = h.cls[c];
-    pl->cls_base[c] = (int32_t)pl->ntasks;
-    pl->ntasks += h.cls[c];
-  }
-  if (pl->ntasks >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 output tiles");
-  pl->c_row = DBuf<int32_t>(ctx, h.nblk);
-  pl->c_col = DBuf<int32_t>(ctx, h.nblk);
-  pl->c_off = DBuf<int64_t>(ctx, h.nblk + 1);
-  pl->cin_off = DBuf<int64_t>(ctx, h.nblk);
-  pl->pptr = DBuf<int64_t>(ctx, h.nblk + 1);
-  pl->px = DBuf<int64_t>(ctx, h.nprod);
-  pl->py = DBuf<int64_t>(ctx, h.nprod);
+  pl->c_row = DBuf<int32_t>(ctx, pl->c_nblk);
+  pl->c_col = DBuf<int32_t>(ctx, pl->c_nblk);
+  pl->c_off = DBuf<int64_t>(ctx, pl->c_nblk + 1);
+  pl->cin_off = DBuf<int64_t>(ctx, pl->c_nblk);
+  pl->pptr = DBuf<int64_t>(ctx, pl->c_nblk + 1);
+  pl->px = DBuf<int64_t>(ctx, pl->nprod);
+  pl->py = DBuf<int64_t>(ctx, pl->nprod);
   pl->tasks = DBuf<int2>(ctx, pl->ntasks);
-  DBuf<int32_t> cursor(ctx, kClasses);
-  hip_check(hipMemsetAsync(cursor.p, 0, sizeof(int32_t) * kClasses, st), "memset");
   if (nr == 0) {  // empty output: write the end markers directly
-    const int64_t z = 0;
+    static const int64_t z = 0;
+    static const int32_t z32 = 0;
+    hip_check(hipMemcpyAsync(pl->c_ptr.p, &z32, sizeof z32, hipMemcpyHostToDevice, st), "copy");
     hip_check(hipMemcpyAsync(pl->c_off.p, &z, sizeof z, hipMemcpyHostToDevice, st), "copy");
     hip_check(hipMemcpyAsync(pl->pptr.p, &z, sizeof z, hipMemcpyHostToDevice, st), "copy");
   }
-  hip_check(launch_sym_fill(st, P, pl->c_ptr.p, el_base.p, prod_base.p, tot.p, cursor.p,
-                            pl->c_row.p, pl->c_col.p, pl->c_off.p, pl->cin_off.p, pl->pptr.p,
-                            pl->px.p, pl->py.p, pl->tasks.p),
+  hip_check(launch_sym_fill(st, P, base.p, pl->c_ptr.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
+                            pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p),
             "symbolic fill");
-  // output block sizes in op space
-  std::vector<int32_t> rs = ta ? A->h_cs : A->h_rs;
-  std::vector<int32_t> cs = tb ? B->h_rs : B->h_cs;
-  pl->c_rs = make_dev(ctx, rs);
-  pl->c_cs = make_dev(ctx, cs);
-  pl->c_same_as_cin = C && h.nblk == C->nblk;
-  // sizes were needed synchronously anyway; keep the index valid before temp buffers return
-  hip_check(hipStreamSynchronize(st), "plan sync");
+  pl->c_same_as_cin = C && pl->c_nblk == C->nblk;
+  // temporaries go back to the allocator: later work on this stream is ordered after the fill
 }
 
 void validate_mm(bsm_pattern A, bsm_pattern B, bsm_pattern C, double eps, const bsm_mm_opts& o) {
@@ -513,8 +157,8 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   P.pptr = pl->pptr.p;
   P.px = pl->px.p;
   P.py = pl->py.p;
-  P.rs = pl->c_rs.p;
-  P.cs = pl->c_cs.p;
+  P.rs = pl->c_rs;
+  P.cs = pl->c_cs;
   P.mx = pl->mx;
   P.my = pl->my;
   P.mo = pl->mo;
@@ -523,11 +167,140 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   const bool generic = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
   P.tasks = pl->tasks.p;
   P.ntasks = (int32_t)pl->ntasks;
-  for (int c = 0; c < kClasses; ++c) P.cls_end[c] = pl->cls_base[c] + pl->cls_cnt[c];
   hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
 }
 
-}  // namespace
+template <class G>
+void for_tiles_host(int m, int n, G&& g) {
+  for (int tr = 0; tr * kTile < m; ++tr)
+    for (int tc = 0; tc * kTile < n; ++tc) g(tr, tc);
+}
+
+// Product lists of the gradient w.r.t. op(A) (which = 0) or op(B) (which = 1):
+// one group per block of that operand, candidates from the other operand.
+void build_grad_lists(bsm_plan pl, int which) {
+  auto& L = pl->grad[which];
+  if (L.built) return;
+  bsm_ctx ctx = pl->ctx;
+  hipStream_t st = ctx->stream;
+  const bool ta = pl->opts.trans_a, tb = pl->opts.trans_b;
+  bsm_pattern A = pl->A, B = pl->B;
+  A->ensure_host();
+  B->ensure_host();
+  bsm_pattern G = which == 0 ? A : B;
+  const bool gt = which == 0 ? ta : tb;
+  if (gt) G->ensure_transpose();
+  if (which == 0 && tb) B->ensure_transpose();
+  if (which == 1 && !ta) A->ensure_transpose();
+  const auto& gptr = gt ? G->h_tptr : G->h_ptr;
+  const auto& gcol = gt ? G->h_trow : G->h_col;
+  const auto& grs = gt ? G->h_cs : G->h_rs;
+  const auto& gcs = gt ? G->h_rs : G->h_cs;
+  const int32_t gnr = gt ? G->nbc : G->nbr;
+  const int64_t ng = G->nblk;
+  std::vector<int32_t> g_row(ng), g_col(ng);
+  std::vector<int64_t> g_off(ng);
+  std::vector<int2> tasks;
+  for (int32_t r = 0; r < gnr; ++r)
+    for (int32_t e = gptr[r]; e < gptr[r + 1]; ++e) {
+      g_row[e] = r;
+      g_col[e] = gcol[e];
+      g_off[e] = G->h_off[gt ? G->h_tblk[e] : G->stored(e)];
+      for_tiles_host(grs[r], gcs[gcol[e]], [&](int tr, int tc) { tasks.push_back(make_int2(e, tr | (tc << 16))); });
+    }
+  const int64_t nt = (int64_t)tasks.size();
+  if (nt >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 gradient tiles");
+  L.g_row = make_dev(ctx, g_row);
+  L.g_col = make_dev(ctx, g_col);
+  L.g_off = make_dev(ctx, g_off);
+  L.tasks = make_dev(ctx, tasks);
+  L.rs = make_dev(ctx, grs);
+  L.cs = make_dev(ctx, gcs);
+  L.ntasks = nt;
+
+  BwdParams P;
+  P.ngrow = gnr;
+  P.g_ptr = gt ? G->d_tptr.p : G->d_ptr.p;
+  P.g_col = gt ? G->d_trow.p : G->d_col.p;
+  P.g_blk = gt ? G->d_tblk.p : (G->h_blk.empty() ? nullptr : G->d_blk.p);
+  P.eps2 = pl->eps * pl->eps;
+  P.g_nrm = which == 0 ? pl->na.p : pl->nb.p;
+  P.db = which;
+  if (which == 0) {  // candidates: op(B) row k
+    P.k_ptr = tb ? B->d_tptr.p : B->d_ptr.p;
+    P.k_col = tb ? B->d_trow.p : B->d_col.p;
+    P.k_blk = tb ? B->d_tblk.p : (B->h_blk.empty() ? nullptr : B->d_blk.p);
+    P.k_nrm = pl->nb.p;
+    P.k_off = B->d_off.p;
+    P.kdim = pl->c_cs;
+  } else {           // candidates: op(A) column k
+    P.k_ptr = ta ? A->d_ptr.p : A->d_tptr.p;
+    P.k_col = ta ? A->d_col.p : A->d_trow.p;
+    P.k_blk = ta ? (A->h_blk.empty() ? nullptr : A->d_blk.p) : A->d_tblk.p;
+    P.k_nrm = pl->na.p;
+    P.k_off = A->d_off.p;
+    P.kdim = pl->c_rs;
+    P.rowq = pl->rowq.p;
+  }
+  P.c_ptr = pl->c_ptr.p;
+  P.c_col = pl->c_col.p;
+  P.c_off = pl->c_off.p;
+  DBuf<int64_t> counts(ctx, ng);
+  L.pptr = DBuf<int64_t>(ctx, ng + 1);
+  hip_check(launch_bwd_lists(st, P, false, counts.p, nullptr, nullptr, nullptr), "gradient count");
+  hip_check(launch_scan_i64(st, ng, counts.p, L.pptr.p), "gradient scan");
+  const int64_t total = download(ctx, L.pptr.p + ng, 1)[0];
+  L.px = DBuf<int64_t>(ctx, total);
+  L.py = DBuf<int64_t>(ctx, total);
+  hip_check(launch_bwd_lists(st, P, true, nullptr, L.pptr.p, L.px.p, L.py.p), "gradient fill");
+  hip_check(hipStreamSynchronize(st), "gradient lists");
+  L.ngroups = ng;
+  L.nprod = total;
+  L.built = true;
+}
+
+int32_t flip_mode(int32_t m) {
+  switch (m) {
+    case kRowMajor: return kColMajor;
+    case kColMajor: return kRowMajor;
+    case kRowSplit: return kColSplit;
+    default: return kRowSplit;
+  }
+}
+
+void execute_grad(bsm_plan pl, int which, double alpha, const double* x, const double* y, double* out) {
+  build_grad_lists(pl, which);
+  auto& L = pl->grad[which];
+  NumParams P;
+  P.out = out;
+  P.X = x;
+  P.Y = y;
+  P.alpha = alpha;
+  P.beta = 0.0;
+  P.c_row = L.g_row.p;
+  P.c_col = L.g_col.p;
+  P.c_off = L.g_off.p;
+  P.pptr = L.pptr.p;
+  P.px = L.px.p;
+  P.py = L.py.p;
+  P.rs = L.rs.p;
+  P.cs = L.cs.p;
+  if (which == 0) {  // dA = dC . op(B)^T
+    P.mo = pl->mx;
+    P.mx = pl->mo;
+    P.my = flip_mode(pl->my);
+    P.rowq = pl->rowq.p;
+  } else {           // dB = op(A)^T . dC
+    P.mo = pl->my;
+    P.mx = flip_mode(pl->mx);
+    P.my = pl->mo;
+  }
+  P.tasks = L.tasks.p;
+  P.ntasks = (int32_t)L.ntasks;
+  hip_check(launch_numeric(pl->ctx->stream, true, P), "gradient numeric");
+}
+
+}  // namespace bsm_host
 
 // ===================================================================== ABI
 
@@ -606,7 +379,8 @@ bsm_status bsm_pattern_export(bsm_pattern p, int32_t* blk_row, int32_t* blk_col,
     p->ensure_host();
     if (blk_row) std::copy(p->h_row.begin(), p->h_row.end(), blk_row);
     if (blk_col) std::copy(p->h_col.begin(), p->h_col.end(), blk_col);
-    if (blk_off) std::copy(p->h_off.begin(), p->h_off.end() - 1, blk_off);
+    if (blk_off)
+      for (int64_t e = 0; e < p->nblk; ++e) blk_off[e] = p->h_off[p->stored(e)];
   });
 }
 
@@ -717,7 +491,8 @@ bsm_status bsm_plan_execute(bsm_plan pl, double alpha, const double* a_vals, con
                             double beta, const double* c_in_vals, double* c_out_vals) {
   return guard([&] {
     if (!pl) fail(BSM_E_INVALID, "NULL plan");
-    execute(pl, alpha, a_vals, b_vals, beta, c_in_vals, c_out_vals);
+    if (pl->ext) pl->ext->exec(pl, alpha, a_vals, b_vals, beta, c_in_vals, c_out_vals);
+    else execute(pl, alpha, a_vals, b_vals, beta, c_in_vals, c_out_vals);
   });
 }
 
@@ -752,24 +527,47 @@ bsm_status bsm_plan_destroy(bsm_plan pl) {
 // Entry points whose implementation lands in later files of this library.
 extern "C" {
 #define BSM_NOT_YET(...) return guard([&] { fail(BSM_E_UNSUPPORTED, "not built yet"); })
-bsm_status bsm_plan_backward(bsm_plan, double, const double*, const double*, const double*, double*,
-                             double*) { BSM_NOT_YET(); }
+bsm_status bsm_plan_backward(bsm_plan pl, double alpha, const double* dc_vals, const double* a_vals,
+                             const double* b_vals, double* da_vals, double* db_vals) {
+  return guard([&] {
+    if (!pl) fail(BSM_E_INVALID, "NULL plan");
+    if (pl->c_nvals > 0 && !dc_vals) fail(BSM_E_INVALID, "NULL dC");
+    if (pl->opts.precision != BSM_PREC_FP64) fail(BSM_E_UNSUPPORTED, "gradient of split precision");
+    set_device(pl->ctx);
+    if (pl->ext) {
+      if ((da_vals && pl->B->nvals > 0 && !b_vals) || (db_vals && pl->A->nvals > 0 && !a_vals))
+        fail(BSM_E_INVALID, "gradient needs the other operand's values");
+      pl->ext->grad(pl, alpha, dc_vals, a_vals, b_vals, da_vals, db_vals);
+      return;
+    }
+    if (da_vals) {
+      if (pl->B->nvals > 0 && !b_vals) fail(BSM_E_INVALID, "dA needs B values");
+      execute_grad(pl, 0, alpha, dc_vals, b_vals, da_vals);
+    }
+    if (db_vals) {
+      if (pl->A->nvals > 0 && !a_vals) fail(BSM_E_INVALID, "dB needs A values");
+      execute_grad(pl, 1, alpha, a_vals, dc_vals, db_vals);
+    }
+  });
+}
+
+bsm_status bsm_plan_cin_grad(bsm_plan pl, double beta, const double* dc_vals, double* dcin_vals) {
+  return guard([&] {
+    if (!pl) fail(BSM_E_INVALID, "NULL plan");
+    if (!pl->Cin || pl->Cin->nblk == 0) return;
+    if (!dc_vals || !dcin_vals) fail(BSM_E_INVALID, "NULL dC or dC_in");
+    set_device(pl->ctx);
+    hip_check(launch_cin_grad(pl->ctx->stream, pl->c_nblk, pl->c_off.p, pl->cin_off.p, beta, dc_vals,
+                              dcin_vals),
+              "dC_in");
+  });
+}
 bsm_status bsm_batch_create(bsm_ctx, int32_t, const bsm_plan*, bsm_batch*) { BSM_NOT_YET(); }
 bsm_status bsm_batch_execute(bsm_batch, const double*, const double*, const double* const*,
                              const double* const*, const double* const*, double* const*, int32_t) {
   BSM_NOT_YET();
 }
 bsm_status bsm_batch_destroy(bsm_batch) { return BSM_OK; }
-bsm_status bsm_tpattern_create(bsm_ctx, int32_t, const int32_t*, const int32_t* const*, int64_t,
-                               const int32_t*, int64_t*, bsm_tpattern*) { BSM_NOT_YET(); }
-bsm_status bsm_tpattern_info(bsm_tpattern, int32_t*, int64_t*, int64_t*) { BSM_NOT_YET(); }
-bsm_status bsm_tpattern_export(bsm_tpattern, int32_t*, int64_t*) { BSM_NOT_YET(); }
-bsm_status bsm_tpattern_destroy(bsm_tpattern) { return BSM_OK; }
-bsm_status bsm_contract_plan(bsm_ctx, const char*, bsm_tpattern, const double*, bsm_tpattern,
-                             const double*, bsm_tpattern, double, const bsm_mm_opts*, bsm_plan*) {
-  BSM_NOT_YET();
-}
-bsm_status bsm_plan_t3_pattern(bsm_plan, bsm_tpattern*) { BSM_NOT_YET(); }
 bsm_status bsm_tune_load(const char*) { BSM_NOT_YET(); }
 bsm_status bsm_tune_get(int32_t*) { BSM_NOT_YET(); }
 bsm_status bsm_tune_set(const int32_t*) { BSM_NOT_YET(); }

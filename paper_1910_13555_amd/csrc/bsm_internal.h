@@ -1,18 +1,20 @@
 // Internal declarations shared by the host planner (bsm_api.cpp) and the
-// device kernels (bsm_kernels.hip).  Not part of the public ABI.
+// device kernels (bsm_symbolic.hip, bsm_numeric.hip, bsm_backward.hip).
+// Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 namespace bsm {
 
 constexpr int kWave = 64;
-constexpr int kSymChunk = 4096;               // output columns per bitmap pass
-constexpr int kSymWords = kSymChunk / 32;
-constexpr int kTile = 32;                     // max output tile edge per task
-constexpr int kClasses = 16;                  // (padded rows/8, padded cols/8) in 1..4 each
+constexpr int kSymChunk = 2048;               // output columns per bitmap pass
+constexpr int kSymWords = kSymChunk / 32;     // = one 32-bit word per lane of a wavefront
+constexpr int kTile = 32;                     // max output tile edge per work item
+constexpr int kSymFields = 6;                 // per-row counts of the symbolic phase
 constexpr uint64_t kMask48 = (uint64_t(1) << 48) - 1;
 
 // Element layout of one block operand, seen as a logical R x C matrix.
@@ -45,11 +47,8 @@ struct SymParams {
   int32_t retain = 0;
 };
 
-// Per-row counts of the symbolic phase and totals read back by the host.
-struct SymTotals {
-  int64_t nblk, nvals, nprod, ncand, flops;
-  int32_t cls[kClasses];
-};
+// Symbolic count fields (k_sym_count / k_scan_fields).
+enum SymField : int { kFBlk = 0, kFVals = 1, kFProd = 2, kFCand = 3, kFFlops = 4, kFTiles = 5 };
 
 struct NumParams {
   double* out = nullptr;
@@ -59,39 +58,63 @@ struct NumParams {
   double alpha = 1.0, beta = 0.0;
   const int32_t* c_row = nullptr; // output block row / column (per output block)
   const int32_t* c_col = nullptr;
-  const int64_t* c_off = nullptr; // output block offsets (nblk + 1)
-  const int64_t* cin_off = nullptr;  // offset of the matching C_in block or -1
+  const int64_t* c_off = nullptr; // output block offsets
+  const int64_t* cin_off = nullptr;  // offset of the matching C_in block or -1 (may be null)
   const int64_t* pptr = nullptr;  // product list per output block (nblk + 1)
   const int64_t* px = nullptr;    // left offset | K << 48
   const int64_t* py = nullptr;    // right offset | q << 48
   const int32_t* rs = nullptr;    // output row sizes
   const int32_t* cs = nullptr;    // output column sizes
-  const int2* tasks = nullptr;    // {output block, tile row | tile col << 16}
+  const int2* tasks = nullptr;    // {output block, tile row | tile col << 16}, canonical order
   int32_t ntasks = 0;
-  int32_t cls_end[kClasses] = {0};  // end of each class's task range (largest class first)
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
   const int32_t* rowq = nullptr;  // split factor per output row block (split layouts)
   int32_t inplace_skip = 0;       // out == cin, beta == 1: blocks without products untouched
 };
 
-// ---- kernel launchers (bsm_kernels.hip); all return the launch status.
+// Product-list construction for the gradient (bsm_backward.hip).
+struct BwdParams {
+  int32_t ngrow = 0;                 // rows of the group pattern (op space)
+  const int32_t* g_ptr = nullptr;    // group CSR (the output operand's blocks)
+  const int32_t* g_col = nullptr;
+  const int32_t* g_blk = nullptr;    // stored index per entry (null: identity)
+  const double* g_nrm = nullptr;     // stored-block norms of the group operand
+  const int32_t* k_ptr = nullptr;    // candidate CSR, indexed by the key
+  const int32_t* k_col = nullptr;    // other output index of each candidate
+  const int32_t* k_blk = nullptr;    // stored index of each candidate (null: identity)
+  const double* k_nrm = nullptr;     // stored-block norms of the candidate operand
+  const int64_t* k_off = nullptr;    // stored offsets of the candidate operand
+  double eps2 = 0.0;
+  int32_t db = 0;                    // 0: groups are op(A) blocks, 1: op(B) blocks
+  const int32_t* c_ptr = nullptr;    // C_out CSR for the (i,j) lookup
+  const int32_t* c_col = nullptr;
+  const int64_t* c_off = nullptr;
+  const int32_t* kdim = nullptr;     // K of each product: n_j (dA) or m_i (dB)
+  const int32_t* rowq = nullptr;     // split factor per row i (dB of split layouts)
+};
+
+// ---- launchers; all return the launch status.
+// bsm_symbolic.hip
 hipError_t launch_block_norms(hipStream_t s, int64_t nblk, const int64_t* off, const double* v,
                               double* out);
-hipError_t launch_sym_count(hipStream_t s, const SymParams& p, int32_t* cnt_blk, int64_t* cnt_el,
-                            int64_t* cnt_prod, int64_t* cnt_cand, int64_t* cnt_flops,
-                            SymTotals* tot);
-hipError_t launch_scan_rows(hipStream_t s, int32_t nr, const int32_t* cnt_blk, const int64_t* cnt_el,
-                            const int64_t* cnt_prod, const int64_t* cnt_cand,
-                            const int64_t* cnt_flops, int32_t* c_ptr, int64_t* el_base,
-                            int64_t* prod_base, SymTotals* tot);
-hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int32_t* c_ptr,
-                           const int64_t* el_base, const int64_t* prod_base, const SymTotals* tot,
-                           int32_t* class_cursor, int32_t* c_row, int32_t* c_col, int64_t* c_off,
-                           int64_t* cin_off_out, int64_t* pptr, int64_t* px, int64_t* py,
-                           int2* tasks);
-// Numeric phase: every tile class in one launch.
+hipError_t launch_sym_count(hipStream_t s, const SymParams& p, int64_t* cnt);
+hipError_t launch_scan_fields(hipStream_t s, int nf, int32_t nr, const int64_t* cnt, int64_t* base,
+                              int64_t* tot);
+hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* base, int32_t* c_ptr,
+                           int32_t* c_row, int32_t* c_col, int64_t* c_off, int64_t* cin_off_out,
+                           int64_t* pptr, int64_t* px, int64_t* py, int2* tasks);
+// bsm_numeric.hip
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);
 hipError_t launch_fill_zero(hipStream_t s, double* p, int64_t n);
-hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+// bsm_backward.hip
+hipError_t launch_bwd_lists(hipStream_t s, const BwdParams& p, bool fill, int64_t* cnt,
+                            const int64_t* pptr, int64_t* px, int64_t* py);
+hipError_t launch_scan_i64(hipStream_t s, int64_t n, const int64_t* in, int64_t* out);
+hipError_t launch_cin_grad(hipStream_t s, int64_t nblk, const int64_t* c_off, const int64_t* cin_off,
+                           double beta, const double* dc, double* dcin);
+// bsm_remap.hip: permute the modes of every block (dims: 4 per block, storage
+// order; perm4[a] = storage mode of target mode a).
+hipError_t launch_remap(hipStream_t s, int64_t nblk, const int64_t* off, const int32_t* dims,
+                        const int32_t* perm4, int inverse, const double* src, double* dst);
 
 }  // namespace bsm

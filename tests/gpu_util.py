@@ -48,3 +48,26 @@ def assert_close(got, ref, tol):
     err = ob.rel_frob_diff(got, ref)
     assert err <= tol, f"relative Frobenius error {err:.3e} > {tol}"
     return err
+
+
+def tensor_to_oracle(pattern, values, mode_sizes):
+    """Library tensor (pattern + device values) as an oracle BlockSparseTensor."""
+    from oracle import tensor as ot
+    idx, offs = pattern.export()
+    vals = values.detach().cpu().numpy()
+    blocks = {}
+    for key, o in zip(idx.tolist(), offs.tolist()):
+        shp = tuple(int(mode_sizes[m][k]) for m, k in enumerate(key))
+        n = int(np.prod(shp))
+        blocks[tuple(key)] = vals[o:o + n].reshape(shp).copy()
+    return ot.BlockSparseTensor(mode_sizes, blocks)
+
+
+def assert_tensor_close(got, ref, tol):
+    from oracle import tensor as ot
+    assert sorted(got.blocks) == sorted(ref.blocks), "tensor patterns differ"
+    num = sum(float(np.sum((got.blocks[k] - ref.blocks[k]) ** 2)) for k in ref.blocks)
+    den = sum(float(np.sum(ref.blocks[k] ** 2)) for k in ref.blocks)
+    err = (num / den) ** 0.5 if den > 0 else num ** 0.5
+    assert err <= tol, f"relative Frobenius error {err:.3e} > {tol}"
+    return err

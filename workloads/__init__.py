@@ -186,3 +186,18 @@ def random_case(rng, nbr: int, nbk: int, nbc: int, sizes=(1, 2, 3, 4),
     B = random_matrix(rng, ksz, csz, occ_b)
     C = random_matrix(rng, rsz, csz, occ_c) if occ_c > 0 else None
     return A, B, C
+
+
+def random_tensor(rng, mode_sizes, occupancy: float):
+    """Random block-sparse tensor: each block slot present with probability
+    ``occupancy``; U[-1,1] values; blocks in lexicographic order."""
+    nbs = [len(s) for s in mode_sizes]
+    total = int(np.prod(nbs))
+    keep = np.nonzero(rng.random(total) < occupancy)[0]
+    idx = np.stack(np.unravel_index(keep, nbs), 1).astype(np.int32) if len(keep) else \
+        np.zeros((0, len(nbs)), np.int32)
+    lens = np.ones(len(idx), np.int64)
+    for m, s in enumerate(mode_sizes):
+        lens *= np.asarray(s, np.int64)[idx[:, m]] if len(idx) else 1
+    vals = rng.uniform(-1.0, 1.0, size=int(lens.sum()) if len(idx) else 0)
+    return dict(mode_sizes=[np.asarray(s, np.int32) for s in mode_sizes], idx=idx, values=vals)
