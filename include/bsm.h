@@ -193,14 +193,21 @@ bsm_status bsm_plan_destroy(bsm_plan plan);
 
 /* ------------------------------------------------------------ batches
  * Many independent multiplies of uneven sizes executed by one persistent
- * kernel launch over a merged, cost-ordered work list (the batches of Sec. 2
- * across problems).  plans: n plans of the same context (all fp64 or all of
- * one split precision).  The batch keeps references to the plans. */
+ * launch per kernel size group over a merged work list, ordered by tile class
+ * (the batches of Sec. 2, across problems).  plans: n >= 1 FP64 matrix plans
+ * of this context (host array) sharing the transposition flags; contraction
+ * plans that need layout remaps are rejected (BSM_E_UNSUPPORTED).  The batch
+ * copies the plans' work items but uses their product lists: every plan must
+ * outlive the batch.  Errors: BSM_E_INVALID for NULL or foreign plans. */
 bsm_status bsm_batch_create(bsm_ctx ctx, int32_t n, const bsm_plan* plans, bsm_batch* out);
-/* alpha, beta: host arrays of n scalars.  a_vals..c_out: host arrays of n
- * device pointers (c_in entries may be NULL where beta is 0).
- * use_graph != 0 captures the launch into a HIP graph on first use and
- * replays it while the pointers and scalars are unchanged. */
+/* alpha, beta: host arrays of n scalars.  a_vals, b_vals, c_out_vals: host
+ * arrays of n device pointers in each plan's value layouts; c_in_vals: host
+ * array of n device pointers (entries may be NULL where beta is 0) or NULL.
+ * Problem p computes what bsm_plan_execute(plans[p], ...) computes.
+ * use_graph != 0 captures the launches into a HIP graph on first use and
+ * replays it while the pointers and scalars are unchanged; the graph runs on
+ * a stream of the batch, ordered after earlier and before later work of the
+ * context's stream.  Not safe to call concurrently on one batch. */
 bsm_status bsm_batch_execute(bsm_batch batch, const double* alpha, const double* beta,
                              const double* const* a_vals, const double* const* b_vals,
                              const double* const* c_in_vals, double* const* c_out_vals,

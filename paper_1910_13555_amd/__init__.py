@@ -25,16 +25,18 @@ from ._lib import BsmError, MmOpts, PlanInfo, check, lib
 
 __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmul",
            "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
-           "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context"]
+           "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
+           "bsm_batch_create", "bsm_batch_execute"]
 
 
-_live = {"plan": weakref.WeakSet(), "pattern": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+_live = {"batch": weakref.WeakSet(), "plan": weakref.WeakSet(), "pattern": weakref.WeakSet(),
+         "ctx": weakref.WeakSet()}
 
 
 @atexit.register
 def _close_all():
     """Release library handles while the HIP runtime is still up."""
-    for kind in ("plan", "pattern", "ctx"):
+    for kind in ("batch", "plan", "pattern", "ctx"):
         for obj in list(_live[kind]):
             try:
                 obj.close()
@@ -265,6 +267,61 @@ def bsm_multiply(ctx: Context, alpha, A: Pattern, a_vals, B: Pattern, b_vals, be
                            float(beta), Cp.handle, _ptr(c_in), _ptr(c_out), float(filter_eps),
                            C.byref(o)))
     return c_out
+
+
+# ----------------------------------------------------------------- batches
+
+class Batch:
+    """Independent multiplies run by one merged persistent launch."""
+
+    def __init__(self, ctx: Context, plans):
+        plans = list(plans)
+        arr = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+        h = C.c_void_p()
+        check(lib.bsm_batch_create(ctx.handle, len(plans), arr, C.byref(h)))
+        self.ctx, self.handle, self.plans = ctx, h, plans
+        _live["batch"].add(self)
+
+    def execute(self, alpha, a_vals, b_vals, beta=None, c_in=None, out=None, use_graph=False):
+        """alpha, beta: one scalar or a list per problem; the value lists hold
+        one tensor per problem (c_in entries may be None where beta is 0)."""
+        n = len(self.plans)
+        al = [float(alpha)] * n if np.isscalar(alpha) else [float(x) for x in alpha]
+        be = [0.0] * n if beta is None else ([float(beta)] * n if np.isscalar(beta) else [float(x) for x in beta])
+        if out is None:
+            out = [torch.empty(p.info["c_nvals"], dtype=torch.float64, device=a_vals[0].device)
+                   for p in self.plans]
+        cin = [None] * n if c_in is None else list(c_in)
+        for p, a, b, ci, o in zip(self.plans, a_vals, b_vals, cin, out):
+            p._check_sizes(a, b, ci, o)
+        if not (len(al) == len(be) == len(a_vals) == len(b_vals) == len(cin) == len(out) == n):
+            raise ValueError("one entry per problem expected")
+        dv = C.c_double * n
+        vp = C.c_void_p * n
+        check(lib.bsm_batch_execute(self.handle, dv(*al), dv(*be), vp(*[_ptr(t) for t in a_vals]),
+                                    vp(*[_ptr(t) for t in b_vals]),
+                                    None if c_in is None else vp(*[_ptr(t) for t in cin]),
+                                    vp(*[_ptr(t) for t in out]), int(bool(use_graph))))
+        return out
+
+    def close(self):
+        if self.handle:
+            check(lib.bsm_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bsm_batch_create(ctx: Context, plans) -> Batch:
+    return Batch(ctx, plans)
+
+
+def bsm_batch_execute(batch: Batch, alpha, a_vals, b_vals, beta=None, c_in=None, out=None, use_graph=False):
+    return batch.execute(alpha, a_vals, b_vals, beta, c_in, out, use_graph)
 
 
 # ------------------------------------------------------- matrix + autograd

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbsm.so")
+# BSM_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("BSM_LIBRARY") or os.path.join(_HERE, "libbsm.so")
 
 BSM_OK = 0
 BSM_E_INVALID = -1

@@ -15,6 +15,33 @@ namespace bsm_host {
 extern const bsm_mm_opts kDefaultOpts;
 const bsm_mm_opts kDefaultOpts = {0, 0, 0, BSM_PREC_FP64};
 
+// Work items of the numeric kernel from a tile list: one per (tile, segment
+// of <= 64 products), written on the device; `seg` ends with their count.
+void build_desc(bsm_ctx ctx, int64_t ntiles, const int2* tiles, const int32_t* c_row,
+                const int32_t* c_col, const int64_t* c_off, const int64_t* cin_off, const int64_t* pptr,
+                const int32_t* rs, const int32_t* cs, const int32_t* rowq, int64_t nprod,
+                int64_t max_tiles_per_block, DBuf<int64_t>& seg, DBuf<TaskDesc>& desc) {
+  hipStream_t st = ctx->stream;
+  DBuf<int64_t> nseg(ctx, ntiles);
+  seg = DBuf<int64_t>(ctx, ntiles + 1);
+  // each tile has max(1, ceil(np / 64)) segments <= 1 + np / 64
+  const int64_t cap = ntiles + max_tiles_per_block * ((nprod + 63) / 64);
+  desc = DBuf<TaskDesc>(ctx, cap);
+  hip_check(launch_count_segments(st, (int32_t)ntiles, tiles, pptr, nseg.p), "segments");
+  DBuf<int64_t> scr(ctx, scan_scratch_size(1, ntiles));
+  hip_check(launch_scan(st, 1, ntiles, nseg.p, seg.p, nullptr, scr.p), "segment scan");
+  hip_check(launch_make_desc(st, (int32_t)ntiles, tiles, seg.p, c_row, c_col, c_off, cin_off, pptr, rs,
+                             cs, rowq, desc.p),
+            "work items");
+}
+
+int64_t max_tiles(const std::vector<int32_t>& rs, const std::vector<int32_t>& cs) {
+  const int32_t mr = rs.empty() ? 1 : *std::max_element(rs.begin(), rs.end());
+  const int32_t mc = cs.empty() ? 1 : *std::max_element(cs.begin(), cs.end());
+  return (int64_t)((mr + kTile - 1) / kTile) * ((mc + kTile - 1) / kTile);
+}
+
+
 OpCsr op_csr(bsm_pattern P, bool trans) {
   OpCsr o;
   if (!trans) {
@@ -79,7 +106,8 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
   DBuf<int64_t> cnt(ctx, (size_t)kSymFields * nr), base(ctx, (size_t)kSymFields * (nr + 1)),
       tot(ctx, kSymFields);
   hip_check(launch_sym_count(st, P, cnt.p), "symbolic count");
-  hip_check(launch_scan_fields(st, kSymFields, nr, cnt.p, base.p, tot.p), "symbolic scan");
+  DBuf<int64_t> scr(ctx, scan_scratch_size(kSymFields, nr));
+  hip_check(launch_scan(st, kSymFields, nr, cnt.p, base.p, tot.p, scr.p), "symbolic scan");
   const std::vector<int64_t> h = download(ctx, tot.p, kSymFields);
   if (h[kFBlk] >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "output has more than 2^31-2 blocks");
   if (h[kFVals] >= (int64_t(1) << 48)) fail(BSM_E_UNSUPPORTED, "output has more than 2^48 values");
@@ -90,6 +118,8 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
   pl->ncand = h[kFCand];
   pl->flops = h[kFFlops];
   pl->ntasks = h[kFTiles];
+  pl->cls_tile[0] = 0;
+  for (int c = 0; c < kClasses; ++c) pl->cls_tile[c + 1] = (int32_t)(pl->cls_tile[c] + h[kFClass + c]);
   pl->c_ptr = DBuf<int32_t>(ctx, nr + 1);
   pl->c_row = DBuf<int32_t>(ctx, pl->c_nblk);
   pl->c_col = DBuf<int32_t>(ctx, pl->c_nblk);
@@ -110,6 +140,9 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                             pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p),
             "symbolic fill");
   pl->c_same_as_cin = C && pl->c_nblk == C->nblk;
+  build_desc(ctx, pl->ntasks, pl->tasks.p, pl->c_row.p, pl->c_col.p, pl->c_off.p, pl->cin_off.p,
+             pl->pptr.p, pl->c_rs, pl->c_cs, pl->rowq.p, pl->nprod,
+             max_tiles(ta ? A->h_cs : A->h_rs, tb ? B->h_rs : B->h_cs), pl->seg, pl->desc);
   // temporaries go back to the allocator: later work on this stream is ordered after the fill
 }
 
@@ -150,23 +183,17 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   P.Y = y;
   P.alpha = alpha;
   P.beta = beta;
-  P.c_row = pl->c_row.p;
-  P.c_col = pl->c_col.p;
-  P.c_off = pl->c_off.p;
-  P.cin_off = pl->cin_off.p;
-  P.pptr = pl->pptr.p;
   P.px = pl->px.p;
   P.py = pl->py.p;
-  P.rs = pl->c_rs;
-  P.cs = pl->c_cs;
   P.mx = pl->mx;
   P.my = pl->my;
   P.mo = pl->mo;
-  P.rowq = pl->rowq.p;
   P.inplace_skip = (out == cin && beta == 1.0) ? 1 : 0;
   const bool generic = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
-  P.tasks = pl->tasks.p;
-  P.ntasks = (int32_t)pl->ntasks;
+  P.desc = pl->desc.p;
+  P.seg = pl->seg.p;
+  std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
+  P.ncu = pl->ctx->ncu;
   hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
 }
 
@@ -200,14 +227,23 @@ void build_grad_lists(bsm_plan pl, int which) {
   const int64_t ng = G->nblk;
   std::vector<int32_t> g_row(ng), g_col(ng);
   std::vector<int64_t> g_off(ng);
-  std::vector<int2> tasks;
+  std::vector<int2> by_class[kClasses];
   for (int32_t r = 0; r < gnr; ++r)
     for (int32_t e = gptr[r]; e < gptr[r + 1]; ++e) {
       g_row[e] = r;
       g_col[e] = gcol[e];
       g_off[e] = G->h_off[gt ? G->h_tblk[e] : G->stored(e)];
-      for_tiles_host(grs[r], gcs[gcol[e]], [&](int tr, int tc) { tasks.push_back(make_int2(e, tr | (tc << 16))); });
+      for_tiles_host(grs[r], gcs[gcol[e]], [&](int tr, int tc) {
+        const int m = std::min(kTile, grs[r] - tr * kTile), n = std::min(kTile, gcs[gcol[e]] - tc * kTile);
+        by_class[tile_class(m, n)].push_back(make_int2(e, tr | (tc << 16)));
+      });
     }
+  std::vector<int2> tasks;
+  L.cls_tile[0] = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    tasks.insert(tasks.end(), by_class[c].begin(), by_class[c].end());
+    L.cls_tile[c + 1] = (int32_t)tasks.size();
+  }
   const int64_t nt = (int64_t)tasks.size();
   if (nt >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 gradient tiles");
   L.g_row = make_dev(ctx, g_row);
@@ -248,11 +284,14 @@ void build_grad_lists(bsm_plan pl, int which) {
   DBuf<int64_t> counts(ctx, ng);
   L.pptr = DBuf<int64_t>(ctx, ng + 1);
   hip_check(launch_bwd_lists(st, P, false, counts.p, nullptr, nullptr, nullptr), "gradient count");
-  hip_check(launch_scan_i64(st, ng, counts.p, L.pptr.p), "gradient scan");
+  DBuf<int64_t> scr(ctx, scan_scratch_size(1, ng));
+  hip_check(launch_scan(st, 1, ng, counts.p, L.pptr.p, nullptr, scr.p), "gradient scan");
   const int64_t total = download(ctx, L.pptr.p + ng, 1)[0];
   L.px = DBuf<int64_t>(ctx, total);
   L.py = DBuf<int64_t>(ctx, total);
   hip_check(launch_bwd_lists(st, P, true, nullptr, L.pptr.p, L.px.p, L.py.p), "gradient fill");
+  build_desc(ctx, nt, L.tasks.p, L.g_row.p, L.g_col.p, L.g_off.p, nullptr, L.pptr.p, L.rs.p, L.cs.p,
+             which == 0 ? pl->rowq.p : nullptr, total, max_tiles(grs, gcs), L.seg, L.desc);
   hip_check(hipStreamSynchronize(st), "gradient lists");
   L.ngroups = ng;
   L.nprod = total;
@@ -277,26 +316,21 @@ void execute_grad(bsm_plan pl, int which, double alpha, const double* x, const d
   P.Y = y;
   P.alpha = alpha;
   P.beta = 0.0;
-  P.c_row = L.g_row.p;
-  P.c_col = L.g_col.p;
-  P.c_off = L.g_off.p;
-  P.pptr = L.pptr.p;
   P.px = L.px.p;
   P.py = L.py.p;
-  P.rs = L.rs.p;
-  P.cs = L.cs.p;
   if (which == 0) {  // dA = dC . op(B)^T
     P.mo = pl->mx;
     P.mx = pl->mo;
     P.my = flip_mode(pl->my);
-    P.rowq = pl->rowq.p;
   } else {           // dB = op(A)^T . dC
     P.mo = pl->my;
     P.mx = flip_mode(pl->mx);
     P.my = pl->mo;
   }
-  P.tasks = L.tasks.p;
-  P.ntasks = (int32_t)L.ntasks;
+  P.desc = L.desc.p;
+  P.seg = L.seg.p;
+  std::copy(L.cls_tile, L.cls_tile + kClasses + 1, P.cls_tile);
+  P.ncu = pl->ctx->ncu;
   hip_check(launch_numeric(pl->ctx->stream, true, P), "gradient numeric");
 }
 
@@ -325,6 +359,10 @@ bsm_status bsm_ctx_create(int32_t device, void* stream, bsm_ctx* out) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
     c->mem.device = device;
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    int ncu = 0;
+    hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device), "CU count");
+    c->ncu = ncu;
     *out = c.release();
   });
 }
@@ -562,12 +600,6 @@ bsm_status bsm_plan_cin_grad(bsm_plan pl, double beta, const double* dc_vals, do
               "dC_in");
   });
 }
-bsm_status bsm_batch_create(bsm_ctx, int32_t, const bsm_plan*, bsm_batch*) { BSM_NOT_YET(); }
-bsm_status bsm_batch_execute(bsm_batch, const double*, const double*, const double* const*,
-                             const double* const*, const double* const*, double* const*, int32_t) {
-  BSM_NOT_YET();
-}
-bsm_status bsm_batch_destroy(bsm_batch) { return BSM_OK; }
 bsm_status bsm_tune_load(const char*) { BSM_NOT_YET(); }
 bsm_status bsm_tune_get(int32_t*) { BSM_NOT_YET(); }
 bsm_status bsm_tune_set(const int32_t*) { BSM_NOT_YET(); }

@@ -77,28 +77,6 @@ __global__ void __launch_bounds__(64) k_bwd_lists(BwdParams P, int64_t* __restri
   }
 }
 
-// Exclusive scan of n int64 counts into out[0..n] (one workgroup).
-__global__ void __launch_bounds__(1024) k_scan_i64(int64_t n, const int64_t* __restrict__ in,
-                                                   int64_t* __restrict__ out) {
-  __shared__ int64_t s[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t r0 = min(n, (int64_t)t * per), r1 = min(n, r0 + per);
-  int64_t v = 0;
-  for (int64_t r = r0; r < r1; ++r) v += in[r];
-  s[t] = v;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int64_t x = t >= d ? s[t - d] : 0;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
-  }
-  int64_t b = s[t] - v;
-  for (int64_t r = r0; r < r1; ++r) { out[r] = b; b += in[r]; }
-  if (t == 1023) out[n] = s[t];
-}
-
 // dC_in = beta * dC on pat(C_in): one wavefront per output block.
 __global__ void __launch_bounds__(256) k_cin_grad(int64_t nblk, const int64_t* __restrict__ c_off,
                                                   const int64_t* __restrict__ cin_off, double beta,
@@ -117,11 +95,6 @@ hipError_t launch_bwd_lists(hipStream_t s, const BwdParams& p, bool fill, int64_
   if (p.ngrow == 0) return hipSuccess;
   if (fill) hipLaunchKernelGGL((k_bwd_lists<true>), dim3(p.ngrow), dim3(64), 0, s, p, cnt, pptr, px, py);
   else hipLaunchKernelGGL((k_bwd_lists<false>), dim3(p.ngrow), dim3(64), 0, s, p, cnt, pptr, px, py);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan_i64(hipStream_t s, int64_t n, const int64_t* in, int64_t* out) {
-  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, s, n, in, out);
   return hipGetLastError();
 }
 

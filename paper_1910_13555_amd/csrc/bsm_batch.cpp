@@ -1,0 +1,196 @@
+// Batches of independent multiplies (the batches of Sec. 2, across problems):
+// the work items of many plans are merged, class by class, into one list and
+// run by one persistent launch per kernel size group; a per-problem table
+// gives each work item its buffers and scalars.  With use_graph the launch is
+// captured into a HIP graph once and replayed while the table is unchanged.
+#include "bsm_host.h"
+
+using namespace bsm;
+using namespace bsm_host;
+
+struct bsm_batch_s {
+  CtxRef ctx;  // first member: released after every buffer below
+  std::vector<bsm_plan> plans;
+  bool generic = false;
+  int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
+  DBuf<TaskDesc> desc;
+  int32_t cls_tile[kClasses + 1] = {0};
+  DBuf<ProbPtrs> ptab;
+  std::vector<ProbPtrs> hptab;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
+  ~bsm_batch_s() {
+    if (ctx && ctx->device >= 0) {
+      (void)hipSetDevice(ctx->device);
+      if (gstream) (void)hipStreamSynchronize(gstream);
+    }
+    drop_graph();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
+};
+
+namespace {
+
+bool same_ptrs(const ProbPtrs& a, const ProbPtrs& b) {
+  return a.out == b.out && a.cin == b.cin && a.X == b.X && a.Y == b.Y && a.px == b.px && a.py == b.py &&
+         a.alpha == b.alpha && a.beta == b.beta && a.inplace_skip == b.inplace_skip;
+}
+
+bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
+  if (n < 1 || !plans) fail(BSM_E_INVALID, "a batch needs at least one plan");
+  auto b = std::make_unique<bsm_batch_s>();
+  b->ctx = ctx;
+  for (int32_t p = 0; p < n; ++p) {
+    bsm_plan pl = plans[p];
+    if (!pl) fail(BSM_E_INVALID, "NULL plan %d", p);
+    if (pl->ctx != ctx) fail(BSM_E_INVALID, "plan %d belongs to another context", p);
+    if (pl->ext) fail(BSM_E_UNSUPPORTED, "plan %d needs layout remaps; batch matrix plans only", p);
+    if (pl->opts.precision != BSM_PREC_FP64) fail(BSM_E_UNSUPPORTED, "batches run in float64");
+    const bool gen = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
+    if (p == 0) { b->generic = gen; b->mx = pl->mx; b->my = pl->my; b->mo = pl->mo; }
+    else if (pl->mx != b->mx || pl->my != b->my || pl->mo != b->mo || gen != b->generic)
+      fail(BSM_E_UNSUPPORTED, "plans of a batch must share transposition flags and layouts");
+    b->plans.push_back(pl);
+  }
+  set_device(ctx);
+  hipStream_t st = ctx->stream;
+  // class boundaries of every plan's work items
+  std::vector<MergeRanges> rng(n);
+  {
+    DBuf<int64_t> bounds(ctx, (size_t)n * (kClasses + 1));
+    for (int32_t p = 0; p < n; ++p) {
+      bsm_plan pl = b->plans[p];
+      for (int c = 0; c <= kClasses; ++c)
+        hip_check(hipMemcpyAsync(bounds.p + (size_t)p * (kClasses + 1) + c, pl->seg.p + pl->cls_tile[c],
+                                 sizeof(int64_t), hipMemcpyDeviceToDevice, st),
+                  "class bounds");
+    }
+    const auto h = download(ctx, bounds.p, (size_t)n * (kClasses + 1));
+    for (int32_t p = 0; p < n; ++p)
+      for (int c = 0; c <= kClasses; ++c) rng[p].sbeg[c] = h[(size_t)p * (kClasses + 1) + c];
+  }
+  int64_t total = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    b->cls_tile[c] = (int32_t)total;
+    for (int32_t p = 0; p < n; ++p) {
+      rng[p].dbeg[c] = total;
+      total += rng[p].sbeg[c + 1] - rng[p].sbeg[c];
+    }
+  }
+  if (total >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 work items in a batch");
+  b->cls_tile[kClasses] = (int32_t)total;
+  b->desc = DBuf<TaskDesc>(ctx, total);
+  for (int32_t p = 0; p < n; ++p)
+    hip_check(launch_merge_desc(st, b->plans[p]->desc.p, rng[p], p, b->desc.p), "merge work items");
+  b->ptab = DBuf<ProbPtrs>(ctx, n);
+  hip_check(hipStreamSynchronize(st), "batch setup");
+  return b.release();
+}
+
+void run_batch(bsm_batch b, const double* alpha, const double* beta, const double* const* a,
+               const double* const* bv, const double* const* cin, double* const* out, int32_t use_graph) {
+  if (!alpha || !beta || !a || !bv || !out) fail(BSM_E_INVALID, "NULL argument array");
+  bsm_ctx ctx = b->ctx;
+  const int32_t n = (int32_t)b->plans.size();
+  std::vector<ProbPtrs> t(n);
+  for (int32_t p = 0; p < n; ++p) {
+    bsm_plan pl = b->plans[p];
+    const double* ci = cin ? cin[p] : nullptr;
+    if (!out[p] && pl->c_nvals > 0) fail(BSM_E_INVALID, "NULL output of problem %d", p);
+    if (beta[p] != 0.0 && pl->Cin && pl->Cin->nblk > 0 && !ci) fail(BSM_E_INVALID, "problem %d: beta != 0 needs C_in", p);
+    if (pl->nprod > 0 && (!a[p] || !bv[p])) fail(BSM_E_INVALID, "problem %d: NULL operand values", p);
+    if (out[p] == ci && ci && !pl->c_same_as_cin)
+      fail(BSM_E_INVALID, "problem %d: c_out may alias c_in only when the output pattern equals C_in's", p);
+    t[p].out = out[p];
+    t[p].cin = ci;
+    t[p].X = a[p];
+    t[p].Y = bv[p];
+    t[p].px = pl->px.p;
+    t[p].py = pl->py.p;
+    t[p].alpha = alpha[p];
+    t[p].beta = beta[p];
+    t[p].inplace_skip = (out[p] == ci && beta[p] == 1.0) ? 1 : 0;
+    t[p].pad = 0;
+  }
+  set_device(ctx);
+  bool changed = b->hptab.size() != t.size();
+  for (int32_t p = 0; !changed && p < n; ++p) changed = !same_ptrs(t[p], b->hptab[p]);
+  if (changed) {
+    hip_check(hipMemcpyAsync(b->ptab.p, t.data(), sizeof(ProbPtrs) * n, hipMemcpyHostToDevice, ctx->stream),
+              "problem table");
+    b->hptab = t;
+    b->drop_graph();
+  }
+  NumParams P;
+  P.desc = b->desc.p;
+  P.seg = nullptr;
+  std::copy(b->cls_tile, b->cls_tile + kClasses + 1, P.cls_tile);
+  P.ptab = b->ptab.p;
+  P.ncu = ctx->ncu;
+  P.mx = b->mx;
+  P.my = b->my;
+  P.mo = b->mo;
+  if (!use_graph) {
+    hip_check(launch_numeric(ctx->stream, b->generic, P), "batch numeric");
+    return;
+  }
+  // graph mode: own stream (capture needs a non-default stream), ordered
+  // after and before the context's stream by events
+  if (!b->gstream) {
+    hip_check(hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking), "stream");
+    hip_check(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "event");
+  }
+  if (!b->gexec) {
+    hip_check(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal), "begin capture");
+    const hipError_t le = launch_numeric(b->gstream, b->generic, P);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->gstream, &g);
+    b->graph = g;
+    hip_check(le, "captured launch");
+    hip_check(ce, "end capture");
+    hip_check(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+  }
+  hip_check(hipEventRecord(b->ev_in, ctx->stream), "event");
+  hip_check(hipStreamWaitEvent(b->gstream, b->ev_in, 0), "wait");
+  hip_check(hipGraphLaunch(b->gexec, b->gstream), "graph launch");
+  hip_check(hipEventRecord(b->ev_out, b->gstream), "event");
+  hip_check(hipStreamWaitEvent(ctx->stream, b->ev_out, 0), "wait");
+}
+
+}  // namespace
+
+extern "C" {
+
+bsm_status bsm_batch_create(bsm_ctx ctx, int32_t n, const bsm_plan* plans, bsm_batch* out) {
+  return guard([&] {
+    if (!ctx || !out) fail(BSM_E_INVALID, "NULL context or output handle");
+    *out = make_batch(ctx, n, plans);
+  });
+}
+
+bsm_status bsm_batch_execute(bsm_batch batch, const double* alpha, const double* beta,
+                             const double* const* a_vals, const double* const* b_vals,
+                             const double* const* c_in_vals, double* const* c_out_vals, int32_t use_graph) {
+  return guard([&] {
+    if (!batch) fail(BSM_E_INVALID, "NULL batch");
+    run_batch(batch, alpha, beta, a_vals, b_vals, c_in_vals, c_out_vals, use_graph);
+  });
+}
+
+bsm_status bsm_batch_destroy(bsm_batch batch) {
+  return guard([&] { delete batch; });
+}
+
+}  // extern "C"

@@ -127,6 +127,7 @@ struct bsm_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int refs = 1;  // the creator's reference plus one per live pattern / plan / batch
+  int ncu = 0;            // compute units of the device
   Allocator mem;
 };
 
@@ -372,8 +373,11 @@ struct bsm_plan_s {
   const int32_t* c_rs = nullptr;  // output block sizes: the operands' device size vectors
   const int32_t* c_cs = nullptr;
   DBuf<int64_t> c_off, cin_off, pptr, px, py;
-  DBuf<int2> tasks;   // output tiles in canonical block order
-  int64_t ntasks = 0;
+  DBuf<int2> tasks;   // output tiles, sorted by tile class
+  int64_t ntasks = 0; // tiles
+  int32_t cls_tile[kClasses + 1] = {0};  // class c's tiles: [cls_tile[c], cls_tile[c+1])
+  DBuf<int64_t> seg;  // segment prefix per tile (ntasks + 1); seg[ntasks] = work items
+  DBuf<TaskDesc> desc;
   DBuf<int32_t> rowq;  // split factors for tensor layouts (optional)
   DBuf<double> na, nb; // stored-block norms of A and B (kept for the gradient when filtering)
   // gradient product lists, built on first use: [0] = dA, [1] = dB
@@ -383,6 +387,9 @@ struct bsm_plan_s {
     DBuf<int32_t> g_row, g_col, rs, cs;
     DBuf<int64_t> g_off, pptr, px, py;
     DBuf<int2> tasks;
+    int32_t cls_tile[kClasses + 1] = {0};
+    DBuf<int64_t> seg;
+    DBuf<TaskDesc> desc;
   } grad[2];
   std::unique_ptr<PlanExt> ext;  // last member: destroyed first
 };

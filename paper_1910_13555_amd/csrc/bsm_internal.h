@@ -14,7 +14,11 @@ constexpr int kWave = 64;
 constexpr int kSymChunk = 2048;               // output columns per bitmap pass
 constexpr int kSymWords = kSymChunk / 32;     // = one 32-bit word per lane of a wavefront
 constexpr int kTile = 32;                     // max output tile edge per work item
-constexpr int kSymFields = 6;                 // per-row counts of the symbolic phase
+constexpr int kClasses = 16;                  // tile classes: padded rows x columns in {8,16,24,32}^2
+constexpr int kSymFields = 6 + kClasses;      // per-row counts of the symbolic phase
+
+// Tile class of an mt x nt tile (1..32 each): (ceil(mt/8)-1)*4 + ceil(nt/8)-1.
+__host__ __device__ inline int tile_class(int mt, int nt) { return ((mt + 7) / 8 - 1) * 4 + ((nt + 7) / 8 - 1); }
 constexpr uint64_t kMask48 = (uint64_t(1) << 48) - 1;
 
 // Element layout of one block operand, seen as a logical R x C matrix.
@@ -47,8 +51,38 @@ struct SymParams {
   int32_t retain = 0;
 };
 
-// Symbolic count fields (k_sym_count / k_scan_fields).
-enum SymField : int { kFBlk = 0, kFVals = 1, kFProd = 2, kFCand = 3, kFFlops = 4, kFTiles = 5 };
+// Symbolic count fields (k_sym_count, then prefix sums); field kFClass + c
+// counts the tiles of class c.
+enum SymField : int { kFBlk = 0, kFVals = 1, kFProd = 2, kFCand = 3, kFFlops = 4, kFTiles = 5, kFClass = 6 };
+
+// One numeric work item: an output tile (at most kTile x kTile of one block)
+// and one segment of at most 64 of the block's products.  Segments of a tile
+// are consecutive; the first zeroes the accumulator, the last writes C.
+constexpr int32_t kTaskFirst = 1, kTaskLast = 2;
+struct TaskDesc {
+  int64_t pbeg;        // first product of the segment
+  int64_t cout;        // offset of the output block
+  int64_t cin;         // offset of the matching C_in block, or -1
+  int32_t np;          // products in the segment (0..64)
+  int32_t flags;       // kTaskFirst | kTaskLast
+  uint16_t M, N;       // output block rows / columns
+  uint16_t tr, tc;     // tile row / column inside the block
+  uint16_t qo;         // split factor of the output row (1 if none)
+  uint16_t cls;        // tile class: (padded rows/8 - 1) * 4 + (padded cols/8 - 1)
+  int32_t pid;         // problem of a batch (index into NumParams::ptab), else 0
+};
+
+// Value buffers and scalars of one problem of a batch.
+struct ProbPtrs {
+  double* out;
+  const double* cin;
+  const double* X;
+  const double* Y;
+  const int64_t* px;
+  const int64_t* py;
+  double alpha, beta;
+  int32_t inplace_skip, pad;
+};
 
 struct NumParams {
   double* out = nullptr;
@@ -56,19 +90,14 @@ struct NumParams {
   const double* X = nullptr;      // left operand values
   const double* Y = nullptr;      // right operand values
   double alpha = 1.0, beta = 0.0;
-  const int32_t* c_row = nullptr; // output block row / column (per output block)
-  const int32_t* c_col = nullptr;
-  const int64_t* c_off = nullptr; // output block offsets
-  const int64_t* cin_off = nullptr;  // offset of the matching C_in block or -1 (may be null)
-  const int64_t* pptr = nullptr;  // product list per output block (nblk + 1)
   const int64_t* px = nullptr;    // left offset | K << 48
   const int64_t* py = nullptr;    // right offset | q << 48
-  const int32_t* rs = nullptr;    // output row sizes
-  const int32_t* cs = nullptr;    // output column sizes
-  const int2* tasks = nullptr;    // {output block, tile row | tile col << 16}, canonical order
-  int32_t ntasks = 0;
+  const TaskDesc* desc = nullptr; // work items, tiles sorted by class
+  const int64_t* seg = nullptr;   // device: first work item of each tile (ntiles + 1); null: one per tile
+  const ProbPtrs* ptab = nullptr; // batches: per-problem buffers and scalars (replace the fields above)
+  int32_t cls_tile[kClasses + 1] = {0};  // class c's tiles: [cls_tile[c], cls_tile[c+1])
+  int32_t ncu = 0;                // compute units (the persistent grids fill them)
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
-  const int32_t* rowq = nullptr;  // split factor per output row block (split layouts)
   int32_t inplace_skip = 0;       // out == cin, beta == 1: blocks without products untouched
 };
 
@@ -98,18 +127,39 @@ struct BwdParams {
 hipError_t launch_block_norms(hipStream_t s, int64_t nblk, const int64_t* off, const double* v,
                               double* out);
 hipError_t launch_sym_count(hipStream_t s, const SymParams& p, int64_t* cnt);
-hipError_t launch_scan_fields(hipStream_t s, int nf, int32_t nr, const int64_t* cnt, int64_t* base,
-                              int64_t* tot);
+// bsm_scan.hip: exclusive prefix sums of nf fields of n int64 counts
+// (in[f*n + r] -> out[f*(n+1) + r], totals at out[f*(n+1) + n] and tot[f] if
+// tot is not null); scratch holds scan_scratch_size(nf, n) int64.
+hipError_t launch_scan(hipStream_t s, int nf, int64_t n, const int64_t* in, int64_t* out, int64_t* tot,
+                       int64_t* scratch);
+int64_t scan_scratch_size(int nf, int64_t n);
 hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* base, int32_t* c_ptr,
                            int32_t* c_row, int32_t* c_col, int64_t* c_off, int64_t* cin_off_out,
                            int64_t* pptr, int64_t* px, int64_t* py, int2* tasks);
 // bsm_numeric.hip
+// Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);
+// Batches: copy one plan's work items (class c at [sbeg[c], sbeg[c+1])) to
+// dbeg[c] of a merged list, tagged with problem pid.
+struct MergeRanges {
+  int64_t sbeg[kClasses + 1];
+  int64_t dbeg[kClasses];
+};
+hipError_t launch_merge_desc(hipStream_t s, const TaskDesc* src, const MergeRanges& r, int32_t pid,
+                             TaskDesc* dst);
+// Work items from a tile list {block, tile row | tile col << 16}: count the
+// product segments per tile, then (after an exclusive scan into seg_base)
+// write the descriptors.
+hipError_t launch_count_segments(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* pptr,
+                                 int64_t* nseg);
+hipError_t launch_make_desc(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* seg_base,
+                            const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
+                            const int64_t* cin_off, const int64_t* pptr, const int32_t* rs,
+                            const int32_t* cs, const int32_t* rowq, TaskDesc* out);
 hipError_t launch_fill_zero(hipStream_t s, double* p, int64_t n);
 // bsm_backward.hip
 hipError_t launch_bwd_lists(hipStream_t s, const BwdParams& p, bool fill, int64_t* cnt,
                             const int64_t* pptr, int64_t* px, int64_t* py);
-hipError_t launch_scan_i64(hipStream_t s, int64_t n, const int64_t* in, int64_t* out);
 hipError_t launch_cin_grad(hipStream_t s, int64_t nblk, const int64_t* c_off, const int64_t* cin_off,
                            double beta, const double* dc, double* dcin);
 // bsm_remap.hip: permute the modes of every block (dims: 4 per block, storage

@@ -7,7 +7,7 @@
 //                   the B row-block it meets (the traversal of Sec. 2) --,
 //                   applies the norm filter and marks output columns in an
 //                   LDS bitmap; counts blocks, values, products and tiles.
-//  * k_scan_fields  exclusive prefix sums of the per-row counts.
+//  (the per-row counts are prefix-summed by bsm_scan.hip)
 //  * k_sym_fill     pass 2: writes the output pattern, each output block's
 //                   product list (its "stack", Sec. 2's batches) ordered by k,
 //                   and the numeric work items in canonical block order.
@@ -52,6 +52,15 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 
 __device__ __forceinline__ int num_tiles(int m, int n) {
   return ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
+}
+
+// Calls f(tile row, tile column, class) for the kTile x kTile tiles of an
+// m x n block.
+template <class F>
+__device__ __forceinline__ void for_tiles(int m, int n, F&& f) {
+  for (int tr = 0; tr * kTile < m; ++tr)
+    for (int tc = 0; tc * kTile < n; ++tc)
+      f(tr, tc, tile_class(min(kTile, m - tr * kTile), min(kTile, n - tc * kTile)));
 }
 
 __device__ __forceinline__ bool bit_test(const uint32_t* bm, int jl) {
@@ -192,11 +201,12 @@ struct CountLds {
   uint32_t bm[kSymWords];
   uint32_t cm[kSymWords];
   int64_t red[kSymThreads / kWave];
+  int cls[kClasses];
   AChunk e;
 };
 
 // Per-row counts in cnt[f * nr + row]: f = 0 blocks, 1 values, 2 products,
-// 3 candidates, 4 useful flops, 5 numeric tiles.
+// 3 candidates, 4 useful flops, 5 numeric tiles, 6 + c tiles of class c.
 __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t* __restrict__ cnt) {
   __shared__ CountLds S;
   const int row = blockIdx.x;
@@ -204,6 +214,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
   const int tid = threadIdx.x;
   const int m = P.rs[row];
   int64_t nblk = 0, nvals = 0, nprod = 0, ncand = 0, flops = 0, ntiles = 0;
+  if (tid < kClasses) S.cls[tid] = 0;
   for (int jlo = 0; jlo < nc; jlo += kSymChunk) {
     const int jhi = min(nc, jlo + kSymChunk);
     if (tid < kSymWords) { S.bm[tid] = 0u; S.cm[tid] = 0u; }
@@ -228,6 +239,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
         ++nblk;
         nvals += n;
         ntiles += num_tiles(m, n);
+        for_tiles(m, n, [&](int, int, int c) { atomicAdd(&S.cls[c], 1); });
       }
     }
     __syncthreads();
@@ -246,48 +258,12 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
     cnt[4 * (int64_t)nr + row] = flops;
     cnt[5 * (int64_t)nr + row] = ntiles;
   }
+  if (tid < kClasses) cnt[(int64_t)(kFClass + tid) * nr + row] = S.cls[tid];
 }
 
 hipError_t launch_sym_count(hipStream_t s, const SymParams& p, int64_t* cnt) {
   if (p.a.nr == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sym_count, dim3(p.a.nr), dim3(kSymThreads), 0, s, p, cnt);
-  return hipGetLastError();
-}
-
-// -------------------------------------------------------------- field scan
-
-// Exclusive prefix sums of nf fields of nr counts each (cnt[f*nr + r]) into
-// base[f*(nr+1) + r], totals into tot[f].  One workgroup.
-__global__ void __launch_bounds__(1024) k_scan_fields(int nf, int32_t nr, const int64_t* __restrict__ cnt,
-                                                      int64_t* __restrict__ base,
-                                                      int64_t* __restrict__ tot) {
-  __shared__ int64_t s[1024];
-  const int t = threadIdx.x;
-  const int per = (nr + 1023) / 1024;
-  const int r0 = min(nr, t * per), r1 = min(nr, r0 + per);
-  for (int f = 0; f < nf; ++f) {
-    const int64_t* c = cnt + (int64_t)f * nr;
-    int64_t* b = base + (int64_t)f * (nr + 1);
-    int64_t v = 0;
-    for (int r = r0; r < r1; ++r) v += c[r];
-    s[t] = v;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-      const int64_t x = t >= d ? s[t - d] : 0;
-      __syncthreads();
-      s[t] += x;
-      __syncthreads();
-    }
-    int64_t acc = s[t] - v;
-    for (int r = r0; r < r1; ++r) { b[r] = acc; acc += c[r]; }
-    if (t == 1023) { b[nr] = s[t]; tot[f] = s[t]; }
-    __syncthreads();
-  }
-}
-
-hipError_t launch_scan_fields(hipStream_t s, int nf, int32_t nr, const int64_t* cnt, int64_t* base,
-                              int64_t* tot) {
-  hipLaunchKernelGGL(k_scan_fields, dim3(1), dim3(1024), 0, s, nf, nr, cnt, base, tot);
   return hipGetLastError();
 }
 
@@ -302,8 +278,10 @@ struct FillLds {
   int colq[kSymChunk];        // column of each output position of the chunk
   int cur[kSymChunk];         // per-position product count, then cursor
   uint64_t mask[kSymChunk];   // A slots (of the current A chunk) hitting each position
-  int npos, ncin, ntile_chunk;
+  int npos, ncin;
   int64_t chunk_el, chunk_prod;
+  int64_t cbase[kClasses];    // first tile of this row in each class's list
+  int ccur[kClasses];         // tiles of this row placed so far, per class
   AChunk e;
 };
 
@@ -312,7 +290,7 @@ __device__ __forceinline__ int rank_in(const uint32_t* bm, const int* pre, int j
   return pre[w] + __popc(bm[w] & ((1u << b) - 1u));
 }
 
-// base: exclusive prefixes (k_scan_fields) for fields 0 blocks, 1 values,
+// base: exclusive prefixes (launch_scan) for fields 0 blocks, 1 values,
 // 2 products, 5 tiles; row r of field f at base[f*(nr+1) + r].
 __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int64_t* __restrict__ base,
                                                           int32_t* __restrict__ c_ptr,
@@ -332,7 +310,12 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
   const int64_t rowblk0 = base[0 * (int64_t)(nr + 1) + row];
   const int64_t rowel0 = base[1 * (int64_t)(nr + 1) + row];
   const int64_t rowprod0 = base[2 * (int64_t)(nr + 1) + row];
-  const int64_t rowtile0 = base[5 * (int64_t)(nr + 1) + row];
+  if (tid < kClasses) {  // class lists follow each other in class order
+    int64_t b = 0;
+    for (int c = 0; c < tid; ++c) b += base[(int64_t)(kFClass + c) * (nr + 1) + nr];
+    S.cbase[tid] = b + base[(int64_t)(kFClass + tid) * (nr + 1) + row];
+    S.ccur[tid] = 0;
+  }
   if (tid == 0) {
     c_ptr[row] = (int32_t)rowblk0;
     if (row == nr - 1) {  // end markers
@@ -344,7 +327,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
   }
   const int cin0 = P.cin_ptr ? P.cin_ptr[row] : 0;
   int pos_base = 0, cin_acc = 0;
-  int64_t el_acc = 0, prod_acc = 0, tile_acc = 0;
+  int64_t el_acc = 0, prod_acc = 0;
   auto keep_of = [&](const Cand& c, int jlo) {
     return c.keep && !(P.retain && !bit_test(S.cm, c.j - jlo));
   };
@@ -398,23 +381,14 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
     }
     for (int q = tid; q < npos; q += blockDim.x) S.cur[q] = 0;
     __syncthreads();
-    // 4. work items (tiles), canonical order
-    if (tid < kWave) {
-      int carry = 0;
-      for (int q0 = 0; q0 < npos; q0 += kWave) {
-        const int q = q0 + tid;
-        const int n = q < npos ? P.cs[S.colq[q]] : 0;
-        const int nt = q < npos ? num_tiles(m, n) : 0;
-        const int incl = wave_incl_scan_i32(nt);
-        if (q < npos) {
-          int64_t w = rowtile0 + tile_acc + carry + incl - nt;
-          const int tcn = (n + kTile - 1) / kTile;
-          for (int u = 0; u < nt; ++u, ++w)
-            tasks[w] = make_int2((int)(rowblk0 + pos_base + q), (u / tcn) | ((u % tcn) << 16));
-        }
-        carry += __shfl(incl, kWave - 1, kWave);
-      }
-      if (tid == 0) S.ntile_chunk = carry;
+    // 4. work items (tiles), sorted by class; within a (row, class) the order
+    //    is free: every tile writes its own output elements
+    for (int q = tid; q < npos; q += blockDim.x) {
+      const int t = (int)(rowblk0 + pos_base + q);
+      for_tiles(m, P.cs[S.colq[q]], [&](int tr, int tc, int c) {
+        const int slot = atomicAdd(&S.ccur[c], 1);
+        tasks[S.cbase[c] + slot] = make_int2(t, tr | (tc << 16));
+      });
     }
     // 5. products per output position
     enum_row(P, row, jlo, jhi, S.e, [&](const Cand& c) {
@@ -466,7 +440,6 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
     pos_base += npos;
     el_acc += S.chunk_el;
     prod_acc += S.chunk_prod;
-    tile_acc += S.ntile_chunk;
     cin_acc += S.ncin;
     __syncthreads();
   }

@@ -17,6 +17,26 @@ def to_oracle(pattern, values, row_sizes, col_sizes):
     return ob.BlockSparse(rs, cs, blocks)
 
 
+def rows_to_oracle(pattern, values, row_sizes, col_sizes, rows):
+    """The blocks of the given block rows of a library result, as an oracle
+    BlockSparse (only those values are copied back)."""
+    prow, pcol, poff = pattern.export()
+    rs = np.asarray(row_sizes, np.int64)
+    cs = np.asarray(col_sizes, np.int64)
+    sel = np.nonzero(np.isin(prow, np.fromiter(rows, np.int64)))[0]
+    if len(sel) == 0:
+        return ob.BlockSparse(rs, cs, {})
+    lens = rs[prow[sel]] * cs[pcol[sel]]
+    idx = np.concatenate([np.arange(o, o + n) for o, n in zip(poff[sel], lens)])
+    vals = values[torch.from_numpy(idx).to(values.device)].cpu().numpy()
+    blocks, pos = {}, 0
+    for e, n in zip(sel.tolist(), lens.tolist()):
+        r, c = int(prow[e]), int(pcol[e])
+        blocks[(r, c)] = vals[pos:pos + n].reshape(rs[r], cs[c]).copy()
+        pos += n
+    return ob.BlockSparse(rs, cs, blocks)
+
+
 def oracle_from_matrix(M):
     """Oracle copy of a library BlockSparseMatrix's inputs (values copied back)."""
     return to_oracle(M.pattern, M.values, M.row_sizes, M.col_sizes)
