@@ -4,9 +4,11 @@ One step = one full multiply C = A.B of the banded workload (2000 x 2000
 blocks of sizes {5,13,23}, band probability 0.5*exp(-|i-j|/40), values
 N(0,1)*exp(-|i-j|/20), filter eps 1e-8): block norms, symbolic phase with the
 single size readback, and the numeric kernel.  Inputs are resident in HBM
-before timing starts.  Prints one JSON line.
+before timing starts.  Prints one JSON line, which also carries the
+split-precision forms on the same workload and the 64-problem batch (FP64 and
+bf16x3, replayed from a HIP graph), each with its error against FP64.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
 """
 from __future__ import annotations
 
@@ -76,12 +78,92 @@ def cpu_baseline(d, nrows=500):
                       f"1 thread, {dt:.1f} s"}
 
 
+def rel_err(x, ref):
+    import torch
+    den = torch.linalg.vector_norm(ref).item()
+    num = torch.linalg.vector_norm(x - ref).item()
+    return num / den if den > 0 else num
+
+
+def time_events(fn, reps, stream):
+    """Average GPU time (ms) of fn() over reps calls, HIP events on the launch stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def split_section(bsm, ctx, A, B, eps, ref, reps, stream):
+    """Split-precision numeric phase on the same workload: rate and error vs the FP64 result."""
+    import torch
+    res = {}
+    for scheme in ("bf16x3", "bf16x6"):
+        plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, None, eps,
+                                     precision=scheme)
+        out = torch.empty(plan.info["c_nvals"], dtype=torch.float64, device=ref.device)
+        plan.execute(1.0, A.values, B.values, 0.0, None, out)
+        ms = time_events(lambda: plan.execute(1.0, A.values, B.values, 0.0, None, out), reps, stream)
+        res[scheme] = {"numeric_ms": ms, "useful_gflops": plan.info["flops"] / (ms * 1e-3) / 1e9,
+                       "rel_frob_err_vs_fp64": rel_err(out, ref)}
+        del plan, out
+    return res
+
+
+def batched_section(bsm, reps, stream):
+    """The 64-problem batch: one merged launch replayed from a HIP graph, in
+    FP64 and again in bf16x3 (error vs the FP64 batch)."""
+    import torch
+    import workloads
+    probs = workloads.batched()
+    ctx = bsm.default_context()
+    mats = [(bsm.BlockSparseMatrix.from_workload(p["A"], ctx=ctx),
+             bsm.BlockSparseMatrix.from_workload(p["B"], ctx=ctx)) for p in probs]
+    a = [m[0].values for m in mats]
+    b = [m[1].values for m in mats]
+    res = {"workload": "batched_64", "problems": len(probs)}
+    ref = None
+    for prec in ("fp64", "bf16x3"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans = [bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, None, p["eps"],
+                                       precision=prec) for (A, B), p in zip(mats, probs)]
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        flops = sum(pl.info["flops"] for pl in plans)
+        batch = bsm.bsm_batch_create(ctx, plans)
+        outs = batch.execute(1.0, a, b, use_graph=True)
+        ms = time_events(lambda: batch.execute(1.0, a, b, out=outs, use_graph=True), reps, stream)
+        ent = {"graph_ms": ms, "useful_gflops": flops / (ms * 1e-3) / 1e9, "plan_s": plan_s,
+               "products": sum(pl.info["nprod"] for pl in plans), "useful_gflop": flops / 1e9}
+        if prec == "fp64":
+            ent["pct_fp64_peak"] = 100.0 * flops / (ms * 1e-3) / PEAK_FP64
+            ref = outs
+        else:
+            num = sum(torch.linalg.vector_norm(o - r).item() ** 2 for o, r in zip(outs, ref))
+            den = sum(torch.linalg.vector_norm(r).item() ** 2 for r in ref)
+            ent["rel_frob_err_vs_fp64"] = (num / den) ** 0.5
+        res[prec] = ent
+        batch.close()
+        del batch, plans
+        if prec != "fp64":
+            del outs
+    del ref
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the split-precision and batched sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -167,8 +249,14 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
                      "traffic": recorded_traffic(),
-                     "kernel": "k_numeric (FP64 4x4x4 matrix-core tiles, all classes, one launch)"},
+                     "kernel": "k_numeric_small (FP64 4x4x4 matrix-core tiles; every tile of this "
+                               "workload is at most 24 x 24)"},
     }
+    if not args.no_extra:
+        res["split"] = split_section(bsm, ctx, A, B, eps, out, args.steps, stream)
+        del plans, plan, out
+        torch.cuda.empty_cache()
+        res["batched"] = batched_section(bsm, max(2, args.steps // 4), stream)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(res), flush=True)

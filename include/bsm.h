@@ -117,7 +117,14 @@ bsm_status bsm_block_norms(bsm_ctx ctx, bsm_pattern p, const double* vals, doubl
  * Options: trans_a/trans_b (0/1) select op(X) = X^T (block (i,j) of X^T is the
  * transpose of stored block (j,i); norms are those of the stored blocks);
  * retain_sparsity (0/1) drops products whose output block is not in C_in;
- * precision is one of BSM_PREC_*. */
+ * precision is one of BSM_PREC_*.  Split precision (not in the paper, whose
+ * only precision is double, Sec. 3): each operand value is rounded to float32
+ * (nearest even) and cut into bfloat16 pieces (nearest even; the remainders
+ * are exact in float32); block products become sums of piece products on the
+ * bfloat16 matrix cores, summed in float32 over chunks of 32 concatenated k
+ * and each chunk added into float64.  Norms, the filter, alpha, beta, C_in
+ * and C_out stay float64.  Split plans need trans_a = trans_b = 0
+ * (BSM_E_UNSUPPORTED otherwise) and have no gradient. */
 typedef struct bsm_mm_opts {
   int32_t trans_a;
   int32_t trans_b;
@@ -194,8 +201,9 @@ bsm_status bsm_plan_destroy(bsm_plan plan);
 /* ------------------------------------------------------------ batches
  * Many independent multiplies of uneven sizes executed by one persistent
  * launch per kernel size group over a merged work list, ordered by tile class
- * (the batches of Sec. 2, across problems).  plans: n >= 1 FP64 matrix plans
- * of this context (host array) sharing the transposition flags; contraction
+ * (the batches of Sec. 2, across problems).  plans: n >= 1 matrix plans of
+ * this context (host array) sharing the transposition flags and the
+ * precision; contraction
  * plans that need layout remaps are rejected (BSM_E_UNSUPPORTED).  The batch
  * copies the plans' work items but uses their product lists: every plan must
  * outlive the batch.  Errors: BSM_E_INVALID for NULL or foreign plans. */

@@ -194,7 +194,8 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   P.seg = pl->seg.p;
   std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
-  hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
+  if (pl->opts.precision == BSM_PREC_FP64) hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
+  else hip_check(launch_numeric_split(pl->ctx->stream, split_pieces(pl->opts.precision), P), "split numeric");
 }
 
 template <class G>
@@ -444,7 +445,8 @@ bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals, c
     const bsm_mm_opts o = opts ? *opts : kDefaultOpts;
     validate_mm(A, B, C_in, filter_eps, o);
     if (A->ctx != ctx) fail(BSM_E_INVALID, "pattern of another context");
-    if (o.precision != BSM_PREC_FP64) fail(BSM_E_UNSUPPORTED, "split precision is not built yet");
+    if (o.precision != BSM_PREC_FP64 && (o.trans_a || o.trans_b))
+      fail(BSM_E_UNSUPPORTED, "split precision needs untransposed operands");
     set_device(ctx);
     auto pl = std::make_unique<bsm_plan_s>();
     pl->ctx = ctx;

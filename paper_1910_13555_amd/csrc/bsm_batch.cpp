@@ -13,6 +13,7 @@ struct bsm_batch_s {
   std::vector<bsm_plan> plans;
   bool generic = false;
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
+  int32_t precision = BSM_PREC_FP64;
   DBuf<TaskDesc> desc;
   int32_t cls_tile[kClasses + 1] = {0};
   DBuf<ProbPtrs> ptab;
@@ -56,11 +57,14 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
     if (!pl) fail(BSM_E_INVALID, "NULL plan %d", p);
     if (pl->ctx != ctx) fail(BSM_E_INVALID, "plan %d belongs to another context", p);
     if (pl->ext) fail(BSM_E_UNSUPPORTED, "plan %d needs layout remaps; batch matrix plans only", p);
-    if (pl->opts.precision != BSM_PREC_FP64) fail(BSM_E_UNSUPPORTED, "batches run in float64");
     const bool gen = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
-    if (p == 0) { b->generic = gen; b->mx = pl->mx; b->my = pl->my; b->mo = pl->mo; }
-    else if (pl->mx != b->mx || pl->my != b->my || pl->mo != b->mo || gen != b->generic)
+    if (p == 0) {
+      b->generic = gen; b->mx = pl->mx; b->my = pl->my; b->mo = pl->mo; b->precision = pl->opts.precision;
+    } else if (pl->mx != b->mx || pl->my != b->my || pl->mo != b->mo || gen != b->generic) {
       fail(BSM_E_UNSUPPORTED, "plans of a batch must share transposition flags and layouts");
+    } else if (pl->opts.precision != b->precision) {
+      fail(BSM_E_UNSUPPORTED, "plans of a batch must share the precision");
+    }
     b->plans.push_back(pl);
   }
   set_device(ctx);
@@ -141,8 +145,12 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   P.mx = b->mx;
   P.my = b->my;
   P.mo = b->mo;
+  auto launch = [&](hipStream_t st) {
+    return b->precision == BSM_PREC_FP64 ? launch_numeric(st, b->generic, P)
+                                         : launch_numeric_split(st, split_pieces(b->precision), P);
+  };
   if (!use_graph) {
-    hip_check(launch_numeric(ctx->stream, b->generic, P), "batch numeric");
+    hip_check(launch(ctx->stream), "batch numeric");
     return;
   }
   // graph mode: own stream (capture needs a non-default stream), ordered
@@ -154,7 +162,7 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   }
   if (!b->gexec) {
     hip_check(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal), "begin capture");
-    const hipError_t le = launch_numeric(b->gstream, b->generic, P);
+    const hipError_t le = launch(b->gstream);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->gstream, &g);
     b->graph = g;

@@ -139,6 +139,10 @@ hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* bas
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);
+// bsm_split.hip: split-precision numeric phase (row-major operands only),
+// npieces bfloat16 pieces per value (2: bf16x3, 3: bf16x6).
+hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p);
+inline int split_pieces(int precision) { return precision == 2 ? 3 : 2; }
 // Batches: copy one plan's work items (class c at [sbeg[c], sbeg[c+1])) to
 // dbeg[c] of a merged list, tagged with problem pid.
 struct MergeRanges {

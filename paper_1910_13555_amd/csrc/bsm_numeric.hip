@@ -21,7 +21,7 @@
 // Every output element has exactly one owner: no atomics, and results are
 // bit-identical from run to run (the GPU counterpart of Sec. 2's static
 // assignment of batches to threads).
-#include "bsm_internal.h"
+#include "bsm_device.h"
 
 namespace bsm {
 
@@ -30,8 +30,6 @@ namespace {
 constexpr int KC = 16;           // k extent per staged chunk
 constexpr int LDA = KC + 1;      // padded row stride of the A stage (doubles)
 constexpr int LDB = kTile + 1;   // padded row stride of the B stage (doubles)
-constexpr int kXcd = 8;          // XCDs per MI355X; workgroups are dealt round-robin
-constexpr int kSeg = 64;         // products per task segment (one per lane)
 // Register budgets (resident wavefronts per SIMD, 512 / n registers per
 // lane): tiles up to 24 x 24 fit three, 32-wide tiles two, without spills.
 constexpr int kWavesSmall = 3;
@@ -43,11 +41,6 @@ struct ClassWaves {
 
 // Classes with 32 padded rows or columns run in the second kernel.
 __host__ __device__ constexpr bool is_big_class(int c) { return c / 4 == 3 || c % 4 == 3; }
-
-struct Rec {       // one product of the front task, with its k offset
-  int64_t xo, yo;
-  int32_t K, kb, q, pad;
-};
 
 struct KEnt {      // source of concatenated-k slot kk of one chunk
   int64_t xo, yo;
@@ -73,31 +66,6 @@ __device__ __forceinline__ int64_t eaddr(int mode, int64_t off, int r, int c, in
     case kRowSplit: { const int u = r / q, p = r - u * q; return off + ((int64_t)u * C + c) * q + p; }
     default: { const int u = c / q, p = c - u * q; return off + ((int64_t)u * R + r) * q + p; }
   }
-}
-
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int l = threadIdx.x;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int t = __shfl_up(v, d, kWave);
-    if (l >= d) v += t;
-  }
-  return v;
-}
-
-// Work item t, read through a wave-uniform index so that it lands in scalar
-// registers.
-__device__ __forceinline__ TaskDesc desc_at(const NumParams& P, int t) {
-  return P.desc[__builtin_amdgcn_readfirstlane(t)];
-}
-
-// Buffers and scalars of problem pid: the batch table, or the launch's own.
-__device__ __forceinline__ ProbPtrs prob(const NumParams& P, int pid) {
-  if (P.ptab) return P.ptab[__builtin_amdgcn_readfirstlane(pid)];
-  ProbPtrs q;
-  q.out = P.out; q.cin = P.cin; q.X = P.X; q.Y = P.Y; q.px = P.px; q.py = P.py;
-  q.alpha = P.alpha; q.beta = P.beta; q.inplace_skip = P.inplace_skip; q.pad = 0;
-  return q;
 }
 
 // The pipelined loop of one tile class (NX x NY instructions of 8x8).
@@ -320,12 +288,7 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
   const int L = (w % kXcd) * (n / kXcd) + w / kXcd;
   const int64_t d0 = P.seg ? P.seg[P.cls_tile[c]] : P.cls_tile[c];
   const int64_t d1 = P.seg ? P.seg[P.cls_tile[c + 1]] : P.cls_tile[c + 1];
-  auto first = [&](int64_t i) {
-    int64_t s = d0 + i * (d1 - d0) / n;
-    while (s < d1 && !(P.desc[s].flags & kTaskFirst)) ++s;
-    return (int)s;
-  };
-  const int t_begin = first(L), t_end = first(L + 1);
+  const int t_begin = slice_start(P.desc, d0, d1, L, n), t_end = slice_start(P.desc, d0, d1, L + 1, n);
   if (t_begin >= t_end) return;
   switch (c) {
 #define BSM_CASE(C_)                                                          \
