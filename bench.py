@@ -78,6 +78,40 @@ def cpu_baseline(d, nrows=500):
                       f"1 thread, {dt:.1f} s"}
 
 
+def traffic_from_counters(fetch_csv, write_csv, copy_bytes, kernel_prefix):
+    """HBM bytes per launch of the numeric kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter read for the plain copy of copy_bytes in the same run.  Writes the
+    result next to the committed profiles, keyed by the kernel source hash."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") == counter:
+                    vals[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        pk = per_kernel(path, counter)
+        copies = [v for k, v in pk.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        mine = [v for k, v in pk.items() if k.startswith(kernel_prefix) or kernel_prefix in k]
+        if not copies or not mine:
+            raise SystemExit(f"{path}: no copy or numeric kernel rows for {counter}")
+        factor = copy_bytes / (max(copies) * 1024.0)
+        out[counter] = {"kib_per_dispatch": mine[0], "copy_kib": max(copies), "scale": factor,
+                        "bytes_per_launch": mine[0] * 1024.0 * factor}
+    rec = {"kernel": kernel_prefix, "kernel_source_sha256_16": kernel_source_hash(),
+           "copy_bytes": copy_bytes, "counters": out,
+           "hbm_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def rel_err(x, ref):
     import torch
     den = torch.linalg.vector_norm(ref).item()
@@ -164,7 +198,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the split-precision and batched sections")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many bytes "
+                         "(calibrates HBM byte counters of a profiler run)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no benchmark: turn two rocprofv3 counter CSVs (taken with --copy-bytes) "
+                         "into the recorded HBM traffic of the numeric kernel")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_bytes,
+                              "void bsm::k_numeric<false, 0>")
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
@@ -175,6 +219,9 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tuned = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "banded.json")
+    if os.path.exists(tuned):
+        bsm.bsm_tune_load(tuned)          # tile-class variants chosen by the autotuner
     dev = torch.device("cuda:0")
     d = workloads.banded()
     A = bsm.BlockSparseMatrix.from_workload(d["A"])
@@ -182,6 +229,13 @@ def main():
     ctx = A.pattern.ctx
     eps = d["eps"]
     stream = torch.cuda.current_stream(dev)
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(ev=None):
         plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, None, eps)

@@ -257,15 +257,21 @@ bsm_status bsm_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, con
 bsm_status bsm_plan_t3_pattern(bsm_plan plan, bsm_tpattern* out);
 
 /* ------------------------------------------------------------ tuning
- * Numeric-kernel variant table: for each output tile class (padded rows,
- * padded columns in {8,16,24,32}) the variant index to use (0 = matrix-core
- * 4x4x4 tile, 1 = matrix-core with LDS-staged operands); see bsm_tune_get.
- * path: JSON file written by the tuner, or NULL to reset to built-in
- * defaults. */
+ * The numeric phase runs each output tile class (padded rows x padded
+ * columns in {8,16,24,32}^2, index (rows/8 - 1) * 4 + columns/8 - 1) with one
+ * of two matrix-core variants: 0 = FP64 4x4x4 in its 4-block form (tiles pad
+ * to multiples of 8), 1 = FP64 16x16x4 (tiles pad to multiples of 16, half
+ * the operand loads per flop).  The table is process-wide and read at each
+ * launch; the autotuner (paper_1910_13555_amd/tune.py) measures both per
+ * class and writes a JSON file {"variant": [16 integers], ...}.
+ * bsm_tune_load(path) reads such a file (BSM_E_INVALID if unreadable or
+ * malformed); path NULL restores the built-in default (16x16x4 where both
+ * padded edges are multiples of 16). */
 bsm_status bsm_tune_load(const char* path);
-/* Current table: out[16] variant per class (row-major over padded rows,
- * columns). */
+/* Current table: out16[c] = variant of class c (host array of 16). */
 bsm_status bsm_tune_get(int32_t* out16);
+/* Replace the table (host array of 16 values in {0, 1}; else BSM_E_INVALID).
+ * Not synchronised with launches in other threads. */
 bsm_status bsm_tune_set(const int32_t* in16);
 
 #ifdef __cplusplus

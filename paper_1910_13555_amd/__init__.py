@@ -26,7 +26,7 @@ from ._lib import BsmError, MmOpts, PlanInfo, check, lib
 __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmul",
            "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
            "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
-           "bsm_batch_create", "bsm_batch_execute"]
+           "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load"]
 
 
 _live = {"batch": weakref.WeakSet(), "plan": weakref.WeakSet(), "pattern": weakref.WeakSet(),
@@ -289,8 +289,8 @@ class Batch:
         al = [float(alpha)] * n if np.isscalar(alpha) else [float(x) for x in alpha]
         be = [0.0] * n if beta is None else ([float(beta)] * n if np.isscalar(beta) else [float(x) for x in beta])
         if out is None:
-            out = [torch.empty(p.info["c_nvals"], dtype=torch.float64, device=a_vals[0].device)
-                   for p in self.plans]
+            dev = torch.device("cuda", self.ctx.device)
+            out = [torch.empty(p.info["c_nvals"], dtype=torch.float64, device=dev) for p in self.plans]
         cin = [None] * n if c_in is None else list(c_in)
         for p, a, b, ci, o in zip(self.plans, a_vals, b_vals, cin, out):
             p._check_sizes(a, b, ci, o)
@@ -322,6 +322,27 @@ def bsm_batch_create(ctx: Context, plans) -> Batch:
 
 def bsm_batch_execute(batch: Batch, alpha, a_vals, b_vals, beta=None, c_in=None, out=None, use_graph=False):
     return batch.execute(alpha, a_vals, b_vals, beta, c_in, out, use_graph)
+
+
+# ------------------------------------------------------------------ tuning
+
+def bsm_tune_get():
+    """Variant per tile class (16 ints: 0 = FP64 4x4x4, 1 = FP64 16x16x4)."""
+    out = np.zeros(16, np.int32)
+    check(lib.bsm_tune_get(_lib.as_i32p(out)))
+    return out.tolist()
+
+
+def bsm_tune_set(variants):
+    arr = np.ascontiguousarray(np.asarray(variants, np.int32))
+    if arr.shape != (16,):
+        raise ValueError("16 variants expected")
+    check(lib.bsm_tune_set(_lib.as_i32p(arr)))
+
+
+def bsm_tune_load(path=None):
+    """Load a tuner JSON file (None: built-in defaults)."""
+    check(lib.bsm_tune_load(None if path is None else str(path).encode()))
 
 
 # ------------------------------------------------------- matrix + autograd

@@ -10,6 +10,9 @@
 // without waiting.
 #include "bsm_host.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 namespace bsm_host {
 
 extern const bsm_mm_opts kDefaultOpts;
@@ -602,7 +605,47 @@ bsm_status bsm_plan_cin_grad(bsm_plan pl, double beta, const double* dc_vals, do
               "dC_in");
   });
 }
-bsm_status bsm_tune_load(const char*) { BSM_NOT_YET(); }
-bsm_status bsm_tune_get(int32_t*) { BSM_NOT_YET(); }
-bsm_status bsm_tune_set(const int32_t*) { BSM_NOT_YET(); }
+bsm_status bsm_tune_load(const char* path) {
+  return guard([&] {
+    int32_t v[kClasses];
+    if (!path) {
+      for (int c = 0; c < kClasses; ++c) v[c] = ((c / 4) % 2 == 1 && (c % 4) % 2 == 1) ? 1 : 0;
+    } else {
+      FILE* f = std::fopen(path, "rb");
+      if (!f) fail(BSM_E_INVALID, "cannot open tuning file %s", path);
+      std::string text;
+      char buf[4096];
+      size_t got;
+      while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+      std::fclose(f);
+      const size_t key = text.find("\"variant\"");
+      const size_t open = key == std::string::npos ? key : text.find('[', key);
+      if (open == std::string::npos) fail(BSM_E_INVALID, "%s: no \"variant\" list", path);
+      const char* q = text.c_str() + open + 1;
+      for (int c = 0; c < kClasses; ++c) {
+        char* end = nullptr;
+        const long x = std::strtol(q, &end, 10);
+        if (end == q) fail(BSM_E_INVALID, "%s: \"variant\" needs %d integers", path, kClasses);
+        v[c] = (int32_t)x;
+        q = end;
+        while (*q == ',' || *q == ' ' || *q == '\n' || *q == '\t' || *q == '\r') ++q;
+      }
+    }
+    if (!set_variants(v)) fail(BSM_E_INVALID, "variants must be 0 or 1");
+  });
+}
+
+bsm_status bsm_tune_get(int32_t* out16) {
+  return guard([&] {
+    if (!out16) fail(BSM_E_INVALID, "NULL output");
+    get_variants(out16);
+  });
+}
+
+bsm_status bsm_tune_set(const int32_t* in16) {
+  return guard([&] {
+    if (!in16) fail(BSM_E_INVALID, "NULL input");
+    if (!set_variants(in16)) fail(BSM_E_INVALID, "variants must be 0 or 1");
+  });
+}
 }

@@ -13,6 +13,16 @@ struct Rec {       // one product of the front task, with its k offset
   int32_t K, kb, q, pad;
 };
 
+// Element (r, c) of an R x C block at off in layout mode (q: split factor).
+__device__ __forceinline__ int64_t eaddr(int mode, int64_t off, int r, int c, int R, int C, int q) {
+  switch (mode) {
+    case kRowMajor: return off + (int64_t)r * C + c;
+    case kColMajor: return off + (int64_t)c * R + r;
+    case kRowSplit: { const int u = r / q, p = r - u * q; return off + ((int64_t)u * C + c) * q + p; }
+    default: { const int u = c / q, p = c - u * q; return off + ((int64_t)u * R + r) * q + p; }
+  }
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int l = threadIdx.x;
 #pragma unroll
@@ -23,15 +33,34 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// Work item t, read through a wave-uniform index so that it lands in scalar
-// registers.
+// Address-space views: global memory (vector memory instructions instead of
+// flat ones), and read-only data that no kernel of the launch writes (scalar
+// loads through the constant address space).
+template <class T>
+using gptr_t = __attribute__((address_space(1))) T*;
+template <class T>
+using cptr_t = __attribute__((address_space(4))) const T*;
+template <class T>
+__device__ __forceinline__ gptr_t<T> gptr(T* p) { return (gptr_t<T>)p; }
+template <class T>
+__device__ __forceinline__ cptr_t<T> cptr(const T* p) { return (cptr_t<T>)p; }
+
+// Work item t, read through a wave-uniform index into scalar registers.
 __device__ __forceinline__ TaskDesc desc_at(const NumParams& P, int t) {
-  return P.desc[__builtin_amdgcn_readfirstlane(t)];
+#if defined(__HIP_DEVICE_COMPILE__)
+  return cptr(P.desc)[__builtin_amdgcn_readfirstlane(t)];
+#else
+  return P.desc[t];  // host pass: never executed
+#endif
 }
 
 // Buffers and scalars of problem pid: the batch table, or the launch's own.
 __device__ __forceinline__ ProbPtrs prob(const NumParams& P, int pid) {
-  if (P.ptab) return P.ptab[__builtin_amdgcn_readfirstlane(pid)];
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (P.ptab) return cptr(P.ptab)[__builtin_amdgcn_readfirstlane(pid)];
+#else
+  if (P.ptab) return P.ptab[pid];  // host pass: never executed
+#endif
   ProbPtrs q;
   q.out = P.out; q.cin = P.cin; q.X = P.X; q.Y = P.Y; q.px = P.px; q.py = P.py;
   q.alpha = P.alpha; q.beta = P.beta; q.inplace_skip = P.inplace_skip; q.pad = 0;

@@ -139,6 +139,10 @@ hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* bas
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);
+// Tuning table of the numeric phase: instruction variant per tile class
+// (0: FP64 4x4x4, 1: FP64 16x16x4); set_variants rejects other values.
+void get_variants(int32_t* out16);
+bool set_variants(const int32_t* in16);
 // bsm_split.hip: split-precision numeric phase (row-major operands only),
 // npieces bfloat16 pieces per value (2: bf16x3, 3: bf16x6).
 hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p);

@@ -2,21 +2,28 @@
 //
 // Work item ("task"): one output tile -- at most 32 x 32 elements of one
 // output block C_ij -- with one segment of at most 64 of that block's
-// products (its stack, Sec. 2).  The k extents of the segment's products are
-// concatenated,
-//     C_ij(tile) = beta * C_in + alpha * [A_ik1 | A_ik2 | ...] . [B_k1j ; B_k2j ; ...],
-// and walked in chunks of 16; chunks are fed to the FP64 4x4x4 matrix-core
-// instruction in its 4-block form, so a tile pads only to multiples of 8 and
-// the k extent only once per segment.
+// products (its stack, Sec. 2), accumulated in registers:
+//     C_ij(tile) = beta * C_in + alpha * sum_k A_ik(tile rows) . B_kj(tile cols).
 //
-// The kernel is persistent.  Tiles are sorted by tile class (padded rows x
-// columns in {8,16,24,32}^2); every wavefront runs the loop compiled for one
-// class over a contiguous range of that class's tasks (contiguous per XCD as
-// well, so neighbouring output blocks -- which share operand blocks -- are
-// served from the same L2).  The range runs as one pipelined stream of
-// chunks: while chunk i is multiplied out of LDS, chunk i+1 is already being
-// gathered into registers, across task boundaries, and the product records
-// of the next task were fetched a whole task earlier.
+// Operands go straight from memory into matrix-core operand registers: each
+// lane loads exactly the A and B elements its lane slot of the instruction
+// needs, with no LDS staging, no tables and no barriers.  A "step" is one
+// product's k range [16 j, 16 j + 16): four instruction k-steps of 4 (steps
+// past the product's K are skipped).  Two instruction shapes:
+//   variant 0: FP64 4x4x4 in its 4-block form -- an 8 x 8 output per
+//              instruction, tiles padded to multiples of 8;
+//   variant 1: FP64 16x16x4 -- a 16 x 16 output per instruction, tiles padded
+//              to multiples of 16, half the operand loads per flop.
+// The variant of each tile class (padded rows x columns in {8,16,24,32}^2)
+// comes from the tuning table.
+//
+// The kernels are persistent: wavefronts own contiguous slices of one
+// class's tasks (contiguous per XCD too, so output blocks that share operand
+// blocks are served from one L2), and run them as one software pipeline of
+// depth D: the loads of step s + D are issued as soon as step s has been
+// multiplied, across task boundaries, and each task's product records are
+// fetched one task ahead.  Unused operand slots read a zero in device memory,
+// so every step issues the same number of loads.
 //
 // Every output element has exactly one owner: no atomics, and results are
 // bit-identical from run to run (the GPU counterpart of Sec. 2's static
@@ -25,321 +32,289 @@
 
 namespace bsm {
 
+// Target of the loads of padding slots (see above).
+__device__ double kZeroD = 0.0;
+__device__ int64_t kZeroL = 0;
+
 namespace {
 
-constexpr int KC = 16;           // k extent per staged chunk
-constexpr int LDA = KC + 1;      // padded row stride of the A stage (doubles)
-constexpr int LDB = kTile + 1;   // padded row stride of the B stage (doubles)
-// Register budgets (resident wavefronts per SIMD, 512 / n registers per
-// lane): tiles up to 24 x 24 fit three, 32-wide tiles two, without spills.
-constexpr int kWavesSmall = 3;
-constexpr int kWavesBig = 2;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int KS = 16;   // k per pipeline step
+
+// Kernels: (variant, tile size) combinations, each with its own pipeline
+// depth and register budget (resident wavefronts per SIMD).
+constexpr int kKernels = 5;
+constexpr int kKernVariant[kKernels] = {0, 0, 0, 1, 1};
+constexpr int kKernDepth[kKernels] = {2, 2, 2, 4, 2};
+constexpr int kKernWaves[kKernels] = {4, 3, 2, 4, 3};
+
+// Kernel of class c under variant v: tiles up to 16 x 16, with 24, with 32
+// (variant 0); 16 x 16, larger (variant 1).
+__host__ __device__ constexpr int kernel_of(int c, int v) {
+  return v == 0 ? ((c / 4 == 3 || c % 4 == 3) ? 2 : (c / 4 == 2 || c % 4 == 2) ? 1 : 0)
+                : ((c / 4 < 2 && c % 4 < 2) ? 3 : 4);
+}
 
 struct ClassWaves {
   int32_t w[kClasses + 1];  // class c's wavefronts: [w[c], w[c+1]) of the grid
 };
 
-// Classes with 32 padded rows or columns run in the second kernel.
-__host__ __device__ constexpr bool is_big_class(int c) { return c / 4 == 3 || c % 4 == 3; }
-
-struct KEnt {      // source of concatenated-k slot kk of one chunk
-  int64_t xo, yo;
-  int32_t K, kq, q, valid;
-};
-
-struct Stage {
-  double A[kTile * LDA];
-  double B[KC * LDB];
-  Rec rec[kSeg];
-  KEnt tab[2][KC];
-  // row-major fast path: per slot, the address of the slot's element in row
-  // 0 of the A block (-1: slot empty), its row stride, and the address of
-  // its row of the B block
-  int64_t a0[2][KC], b0[2][KC];
-  int32_t ak[2][KC];
-};
-
-__device__ __forceinline__ int64_t eaddr(int mode, int64_t off, int r, int c, int R, int C, int q) {
-  switch (mode) {
-    case kRowMajor: return off + (int64_t)r * C + c;
-    case kColMajor: return off + (int64_t)c * R + r;
-    case kRowSplit: { const int u = r / q, p = r - u * q; return off + ((int64_t)u * C + c) * q + p; }
-    default: { const int u = c / q, p = c - u * q; return off + ((int64_t)u * R + r) * q + p; }
-  }
-}
-
-// The pipelined loop of one tile class (NX x NY instructions of 8x8).
-// Gather layout: A slot s holds row 4s + l/16 at chunk slot l%16;
-// B slot s holds (kk, c) = divmod(64s + l, TN).
-template <int NX, int NY, bool GEN>
-__device__ void run_class(const NumParams& P, Stage& S, int t_begin, int t_end) {
-  constexpr int TN = 8 * NY;
-  constexpr int SA = 2 * NX, SB = 2 * NY;
+// Pipelined loop over this wavefront's tiles of one class; NI x NJ
+// instructions per tile (8 x 8 outputs each for V = 0, 16 x 16 for V = 1).
+// The wavefront owns the tiles whose first work item sits at e0 + r,
+// e0 + r + stride, ... inside [e0, e1), each with the work items that
+// continue it.
+template <int V, int NI, int NJ, bool GEN, int D>
+__device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, int r, int stride) {
   const int l = threadIdx.x;
-  const int li = l & 3, lb = (l >> 2) & 3, lk = l >> 4;
+  // lane roles: rows (A) / columns (B) and instruction k index
+  const int lrA = V == 0 ? 4 * ((l >> 3) & 1) + (l & 3) : (l & 15);   // row inside an instruction tile
+  const int lcB = V == 0 ? 4 * ((l >> 2) & 1) + (l & 3) : (l & 15);   // column inside an instruction tile
+  const int lk = V == 0 ? (l >> 4) : (l >> 4);                        // k inside an instruction k-step
+  constexpr int TI = V == 0 ? 8 : 16;                                  // instruction tile edge
 
-  auto load_recs = [&](int t, int64_t& xw, int64_t& yw) {
-    const TaskDesc d = desc_at(P, t);
-    const ProbPtrs pp = prob(P, d.pid);
-    xw = 0;
-    yw = 0;
-    if (l < d.np) { xw = pp.px[d.pbeg + l]; yw = pp.py[d.pbeg + l]; }
+  // ---- issue side: cursor over (work item, product, k step)
+  int own = e0 + r;                        // own slot of the current tile
+  while (own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
+  if (own >= e1) return;
+  // the work item after `it`: the tile's next segment, else the next own tile
+  auto next_item = [&](int it) __attribute__((always_inline)) {
+    if (it + 1 < e1 && !(desc_at(P, it + 1).flags & kTaskFirst)) return it + 1;
+    own += stride;
+    while (own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
+    return min(own, e1);
   };
-  // Records into LDS with their k offsets; returns the task's chunk count
-  // (at least 1, so a task without products still writes its output).
-  auto publish_recs = [&](int64_t xw, int64_t yw) {
-    const int K = (int)((uint64_t)xw >> 48);
-    const int incl = wave_incl_scan(K);
-    Rec r;
-    r.xo = (int64_t)((uint64_t)xw & kMask48);
-    r.yo = (int64_t)((uint64_t)yw & kMask48);
-    r.K = K;
-    r.kb = incl - K;
-    r.q = (int)((uint64_t)yw >> 48);
-    r.pad = 0;
-    S.rec[l] = r;
-    const int total = __shfl(incl, kWave - 1, kWave);
-    return max(1, (total + KC - 1) / KC);
+  int it = own, ip = 0, ij = 0;
+  TaskDesc id = desc_at(P, it);
+  ProbPtrs ipp = prob(P, id.pid);
+  int64_t rx, ry, nrx = 0, nry = 0;
+  auto fetch = [&](const TaskDesc& d, const ProbPtrs& pp, int64_t& xw, int64_t& yw) __attribute__((always_inline)) {
+    const bool ok = l < d.np;
+    xw = *(ok ? gptr(pp.px) + d.pbeg + l : gptr(&kZeroL));
+    yw = *(ok ? gptr(pp.py) + d.pbeg + l : gptr(&kZeroL));
   };
-  // Slot table of chunk c of the front task (lanes 0..15), from S.rec.
-  auto build_tab = [&](int buf, int c, const TaskDesc& d) {
-    if (l < KC) {
-      const int k = c * KC + l;
-      KEnt e;
-      e.valid = 0; e.xo = 0; e.yo = 0; e.K = 1; e.kq = 0; e.q = 1;
-      if (d.np > 0) {
-        int lo = 0, hi = d.np - 1;           // last product with kb <= k
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (S.rec[mid].kb <= k) lo = mid; else hi = mid - 1;
-        }
-        const Rec& r = S.rec[lo];
-        if (k - r.kb < r.K) {
-          e.valid = 1; e.xo = r.xo; e.yo = r.yo; e.K = r.K; e.kq = k - r.kb; e.q = r.q;
-        }
-      }
-      if (GEN) {
-        S.tab[buf][l] = e;
-      } else {
-        S.a0[buf][l] = e.valid ? e.xo + (int64_t)(d.tr * kTile) * e.K + e.kq : -1;
-        S.ak[buf][l] = e.K;
-        S.b0[buf][l] = e.valid ? e.yo + (int64_t)e.kq * d.N + d.tc * kTile : -1;
+  fetch(id, ipp, rx, ry);
+  int nit = next_item(it);                 // the work item after it, records prefetched
+  if (nit < e1) {
+    const TaskDesc nd = desc_at(P, nit);
+    fetch(nd, prob(P, nd.pid), nrx, nry);
+  }
+
+  double A[D][NI][4], B[D][NJ][4];
+  TaskDesc td[D];
+  int tflag[D], tnks[D];
+
+  auto issue = [&](double (&a)[NI][4], double (&b)[NJ][4], TaskDesc& tdk, int& flag, int& nks)
+                   __attribute__((always_inline)) {
+    if (it >= e1) { flag = 0; return; }
+    int64_t xo = 0, yo = 0;
+    int K = 0, q = 1;
+    if (id.np > 0) {
+      const uint32_t xl = __builtin_amdgcn_readlane((int)(uint32_t)rx, ip);
+      const uint32_t xh = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)rx >> 32), ip);
+      const uint32_t yl = __builtin_amdgcn_readlane((int)(uint32_t)ry, ip);
+      const uint32_t yh = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)ry >> 32), ip);
+      xo = (int64_t)(((uint64_t)(xh & 0xffffu) << 32) | xl);
+      K = (int)(xh >> 16);
+      yo = (int64_t)(((uint64_t)(yh & 0xffffu) << 32) | yl);
+      q = (int)(yh >> 16);
+    }
+    const int k0 = KS * ij;
+    const int kv = id.np > 0 ? min(KS, K - k0) : 0;      // valid k of this step
+    const int r0 = id.tr * kTile, c0 = id.tc * kTile;
+    const int mt = min(kTile, (int)id.M - r0), nt = min(kTile, (int)id.N - c0);
+    const int qa = P.mx == kRowSplit ? (int)id.qo : q;
+#pragma unroll
+    for (int x = 0; x < NI; ++x) {
+      const int r = TI * x + lrA;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kq = 4 * ks + lk;
+        const bool v = r < mt && kq < kv;
+        const int64_t ad = GEN ? eaddr(P.mx, xo, r0 + r, k0 + kq, id.M, K, qa)
+                               : xo + (int64_t)(r0 + r) * K + k0 + kq;
+        a[x][ks] = *(v ? gptr(ipp.X) + ad : gptr(&kZeroD));
       }
     }
-  };
-  double ga[SA], gb[SB];
-  auto gather = [&](int buf, const TaskDesc& d) {
-    const int r0 = d.tr * kTile, c0 = d.tc * kTile;
-    const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
-    const ProbPtrs pp = prob(P, d.pid);
-    if (GEN) {
-      const KEnt e = S.tab[buf][l % KC];
 #pragma unroll
-      for (int s = 0; s < SA; ++s) {
-        const int r = 4 * s + l / KC;
-        ga[s] = (e.valid && r < mt)
-                    ? pp.X[eaddr(P.mx, e.xo, r0 + r, e.kq, d.M, e.K, P.mx == kRowSplit ? (int)d.qo : e.q)]
-                    : 0.0;
-      }
+    for (int y = 0; y < NJ; ++y) {
+      const int c = TI * y + lcB;
 #pragma unroll
-      for (int s = 0; s < SB; ++s) {
-        const int idx = s * kWave + l;
-        const int kk = idx / TN, c = idx % TN;
-        const KEnt& f = S.tab[buf][kk];
-        gb[s] = (f.valid && c < nt) ? pp.Y[eaddr(P.my, f.yo, f.kq, c0 + c, f.K, d.N, f.q)] : 0.0;
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kq = 4 * ks + lk;
+        const bool v = c < nt && kq < kv;
+        const int64_t ad = GEN ? eaddr(P.my, yo, k0 + kq, c0 + c, K, id.N, q)
+                               : yo + (int64_t)(k0 + kq) * id.N + c0 + c;
+        b[y][ks] = *(v ? gptr(ipp.Y) + ad : gptr(&kZeroD));
       }
+    }
+    tdk = id;
+    nks = (kv + 3) / 4;
+    flag = 1;
+    // advance the cursor
+    if (id.np > 0 && k0 + KS < K) {
+      ++ij;
     } else {
-      const int64_t a0 = S.a0[buf][l % KC];
-      const int64_t ak = S.ak[buf][l % KC];
-      const double* xa = pp.X + a0 + (l / KC) * ak;
-#pragma unroll
-      for (int s = 0; s < SA; ++s) {
-        const int r = 4 * s + l / KC;
-        ga[s] = (a0 >= 0 && r < mt) ? xa[4 * s * ak] : 0.0;
+      ij = 0;
+      if (++ip >= id.np) {
+        if (id.flags & kTaskLast) flag |= 2;  // the tile's last step: write it out
+        ip = 0;
+        it = nit;
+        if (it < e1) {
+          id = desc_at(P, it);
+          ipp = prob(P, id.pid);
+          rx = nrx;
+          ry = nry;
+          nit = next_item(it);
+          if (nit < e1) {
+            const TaskDesc nd = desc_at(P, nit);
+            fetch(nd, prob(P, nd.pid), nrx, nry);
+          }
+        }
       }
-#pragma unroll
-      for (int s = 0; s < SB; ++s) {
-        const int idx = s * kWave + l;
-        const int kk = idx / TN, c = idx % TN;
-        const int64_t b0 = S.b0[buf][kk];
-        gb[s] = (b0 >= 0 && c < nt) ? pp.Y[b0 + c] : 0.0;
-      }
     }
   };
-  auto stage = [&]() {
+
+  // ---- compute side
+  using Acc = typename std::conditional<V == 0, double, f64x4>::type;
+  Acc acc[NI][NJ];
 #pragma unroll
-    for (int s = 0; s < SA; ++s) S.A[(4 * s + l / KC) * LDA + l % KC] = ga[s];
+  for (int x = 0; x < NI; ++x)
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      const int idx = s * kWave + l;
-      S.B[(idx / TN) * LDB + idx % TN] = gb[s];
-    }
-  };
-  // Lane l = i + 4b + 16k of the 4x4x4 instruction: A holds rows
-  // 8x+4(b/2)+i, B columns 8y+4(b%2)+i, both at k = l/16; the result of
-  // sub-tile element (r,c) is at lane c + 4b + 16r.
-  double acc[NX][NY];
-#pragma unroll
-  for (int x = 0; x < NX; ++x)
-#pragma unroll
-    for (int y = 0; y < NY; ++y) acc[x][y] = 0.0;
-  auto mma = [&]() {
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      double a[NX], b[NY];
-#pragma unroll
-      for (int x = 0; x < NX; ++x) a[x] = S.A[(8 * x + 4 * (lb >> 1) + li) * LDA + 4 * ks + lk];
-#pragma unroll
-      for (int y = 0; y < NY; ++y) b[y] = S.B[(4 * ks + lk) * LDB + 8 * y + 4 * (lb & 1) + li];
-#pragma unroll
-      for (int x = 0; x < NX; ++x)
-#pragma unroll
-        for (int y = 0; y < NY; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
-    }
-  };
-  auto epilogue = [&](const TaskDesc& d) {
+    for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
+  auto epilogue = [&](const TaskDesc& d) __attribute__((always_inline)) {
     const int r0 = d.tr * kTile, c0 = d.tc * kTile;
     const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
     const ProbPtrs pp = prob(P, d.pid);
     const bool use_cin = pp.beta != 0.0 && d.cin >= 0;
     const bool write = !(pp.inplace_skip && d.np == 0);
 #pragma unroll
-    for (int x = 0; x < NX; ++x) {
-      const int r = 8 * x + 4 * (lb >> 1) + lk;
+    for (int x = 0; x < NI; ++x)
 #pragma unroll
-      for (int y = 0; y < NY; ++y) {
-        const int c = 8 * y + 4 * (lb & 1) + li;
-        if (write && r < mt && c < nt) {
-          const int64_t rel = GEN ? eaddr(P.mo, 0, r0 + r, c0 + c, d.M, d.N, d.qo)
-                                  : (int64_t)(r0 + r) * d.N + c0 + c;
-          double v = pp.alpha * acc[x][y];
-          if (use_cin) v += pp.beta * pp.cin[d.cin + rel];
-          pp.out[d.cout + rel] = v;
+      for (int y = 0; y < NJ; ++y) {
+        constexpr int NE = V == 0 ? 1 : 4;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          // variant 0: lane j + 4b + 16i holds (4(b/2) + i, 4(b%2) + j) of
+          // the 8 x 8 tile; variant 1: element e of lane l is (4e + l/16, l%16)
+          const int r = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+          const int c = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+          double av;
+          if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
+          if (write && r < mt && c < nt) {
+            const int64_t rel = GEN ? eaddr(P.mo, 0, r0 + r, c0 + c, d.M, d.N, d.qo)
+                                    : (int64_t)(r0 + r) * d.N + c0 + c;
+            double v = pp.alpha * av;
+            if (use_cin) v += pp.beta * gptr(pp.cin)[d.cin + rel];
+            gptr(pp.out)[d.cout + rel] = v;
+          }
         }
-        acc[x][y] = 0.0;
+        acc[x][y] = Acc{};
+      }
+  };
+  auto compute = [&](const double (&a)[NI][4], const double (&b)[NJ][4], int nks) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (ks < nks) {
+#pragma unroll
+        for (int x = 0; x < NI; ++x)
+#pragma unroll
+          for (int y = 0; y < NJ; ++y) {
+            if constexpr (V == 0)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+            else
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+          }
       }
     }
   };
 
-  // front = item being gathered, back = item being multiplied (one behind)
-  int fi = t_begin, fc = 0;
-  TaskDesc fd = desc_at(P, fi);
-  int64_t nxw, nyw;                        // prefetched records of task fi + 1
-  load_recs(fi, nxw, nyw);
-  int fn = publish_recs(nxw, nyw);
-  int nch0 = 0, nch1 = 0;                  // chunk counts of back / front tasks by parity
-  auto set_nch = [&](int t, int v) { if (t & 1) nch1 = v; else nch0 = v; };
-  set_nch(fi, fn);
-  if (fi + 1 < t_end) load_recs(fi + 1, nxw, nyw);
-  int tb = 0;
-  __syncthreads();
-  build_tab(tb, 0, fd);
-  __syncthreads();
-  gather(tb, fd);
-
-  int bi = fi, bc = 0;
-  TaskDesc bd = fd;
-  while (true) {
-    __syncthreads();                       // previous chunk consumed
-    stage();
-    bool more = true;
-    if (fc + 1 < fn) {
-      ++fc;
-    } else if (fi + 1 < t_end) {
-      ++fi;
-      fc = 0;
-      fd = desc_at(P, fi);
-      fn = publish_recs(nxw, nyw);         // records fetched one task ago
-      set_nch(fi, fn);
-      if (fi + 1 < t_end) load_recs(fi + 1, nxw, nyw);
-      __syncthreads();                     // records visible to the table builders
-    } else {
-      more = false;
-    }
-    tb ^= 1;
-    if (more) build_tab(tb, fc, fd);
-    __syncthreads();                       // stage and table visible
-    if (more) gather(tb, fd);              // in flight during the products below
-    mma();
-    if (bc + 1 == ((bi & 1) ? nch1 : nch0)) {
-      if (bd.flags & kTaskLast) epilogue(bd);
-      if (!more) break;
-      ++bi;
-      bc = 0;
-      bd = desc_at(P, bi);
-    } else {
-      ++bc;
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue(A[d], B[d], td[d], tflag[d], tnks[d]);
+  bool done = false;
+  while (!done) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (!done) {
+        if (!(tflag[d] & 1)) {
+          done = true;
+        } else {
+          compute(A[d], B[d], tnks[d]);
+          if (tflag[d] & 2) epilogue(td[d]);
+          issue(A[d], B[d], td[d], tflag[d], tnks[d]);
+        }
+      }
     }
   }
 }
 
-// Persistent kernels.  Wavefronts [cls_wave[c], cls_wave[c+1]) serve class c
-// (a multiple of 8 of them); local wavefront w takes the logical slice
-// (w % 8) * (n / 8) + w / 8 of the class's work items, so each XCD owns one
-// contiguous eighth.  Slices start and end on a tile's first segment.
-template <bool GEN, bool BIG>
-__device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* cls_wave, Stage& S) {
+// Persistent kernel KID.  Wavefronts [W.w[c], W.w[c+1]) serve class c (a
+// multiple of 8 of them).  Workgroups are dealt to the 8 XCDs round-robin, so
+// local wavefront w runs on XCD w % 8; each XCD owns one contiguous eighth of
+// the class's work items (cut at tile starts), and its wavefronts take that
+// eighth's tiles cyclically.  All wavefronts of an XCD therefore work on
+// neighbouring output blocks at any moment, and the operand blocks those
+// share stay in the XCD's L2.
+template <bool GEN, int KID>
+__device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* cls_wave) {
   const int b = blockIdx.x;
   int c = 0;
   while (c < kClasses - 1 && b >= cls_wave[c + 1]) ++c;
   const int n = cls_wave[c + 1] - cls_wave[c];
   const int w = b - cls_wave[c];
-  const int L = (w % kXcd) * (n / kXcd) + w / kXcd;
+  const int x = w % kXcd, r = w / kXcd;
   const int64_t d0 = P.seg ? P.seg[P.cls_tile[c]] : P.cls_tile[c];
   const int64_t d1 = P.seg ? P.seg[P.cls_tile[c + 1]] : P.cls_tile[c + 1];
-  const int t_begin = slice_start(P.desc, d0, d1, L, n), t_end = slice_start(P.desc, d0, d1, L + 1, n);
-  if (t_begin >= t_end) return;
-  switch (c) {
-#define BSM_CASE(C_)                                                          \
-  case C_:                                                                    \
-    if (is_big_class(C_) == BIG) run_class<C_ / 4 + 1, C_ % 4 + 1, GEN>(P, S, t_begin, t_end); \
+  const int e0 = slice_start(P.desc, d0, d1, x, kXcd), e1 = slice_start(P.desc, d0, d1, x + 1, kXcd);
+  if (e0 + r >= e1) return;
+  constexpr int V = kKernVariant[KID];
+  constexpr int DP = kKernDepth[KID];
+  // one call per distinct instruction grid of this kernel's classes
+  const int ni = V == 0 ? c / 4 + 1 : (c / 4 + 2) / 2;
+  const int nj = V == 0 ? c % 4 + 1 : (c % 4 + 2) / 2;
+  switch (ni * 8 + nj) {
+#define BSM_SHAPE(NI_, NJ_)                                                              \
+  case NI_ * 8 + NJ_:                                                                    \
+    if constexpr (V == 0 ? kernel_of((NI_ - 1) * 4 + NJ_ - 1, 0) == KID                  \
+                         : kernel_of((2 * NI_ - 1) * 4 + 2 * NJ_ - 1, 1) == KID)         \
+      run_tiles<V, NI_, NJ_, GEN, DP>(P, e0, e1, r, n / kXcd);                            \
     break;
-    BSM_CASE(0) BSM_CASE(1) BSM_CASE(2) BSM_CASE(3)
-    BSM_CASE(4) BSM_CASE(5) BSM_CASE(6) BSM_CASE(7)
-    BSM_CASE(8) BSM_CASE(9) BSM_CASE(10) BSM_CASE(11)
-    BSM_CASE(12) BSM_CASE(13) BSM_CASE(14) BSM_CASE(15)
-#undef BSM_CASE
+    BSM_SHAPE(1, 1) BSM_SHAPE(1, 2) BSM_SHAPE(1, 3) BSM_SHAPE(1, 4)
+    BSM_SHAPE(2, 1) BSM_SHAPE(2, 2) BSM_SHAPE(2, 3) BSM_SHAPE(2, 4)
+    BSM_SHAPE(3, 1) BSM_SHAPE(3, 2) BSM_SHAPE(3, 3) BSM_SHAPE(3, 4)
+    BSM_SHAPE(4, 1) BSM_SHAPE(4, 2) BSM_SHAPE(4, 3) BSM_SHAPE(4, 4)
+#undef BSM_SHAPE
   }
 }
 
 }  // namespace
 
-// Tiles up to 24 x 24 (three resident wavefronts per SIMD without spills).
-template <bool GEN>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesSmall)))
-k_numeric_small(NumParams P, ClassWaves W) {
-  __shared__ Stage S;
-  numeric_body<GEN, false>(P, W.w, S);
-}
-
-// Tiles with 32 rows or columns (two resident wavefronts per SIMD).
-template <bool GEN>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesBig)))
-k_numeric_big(NumParams P, ClassWaves W) {
-  __shared__ Stage S;
-  numeric_body<GEN, true>(P, W.w, S);
+template <bool GEN, int KID>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kKernWaves[KID])))
+k_numeric(NumParams P, ClassWaves W) {
+  numeric_body<GEN, KID>(P, W.w);
 }
 
 namespace {
 
-// Resident wavefronts per CU for a register budget, within the LDS limit of
-// 160 KB / sizeof(Stage).
-int waves_per_cu(int per_simd) { return std::min<int>(4 * per_simd, (160 * 1024) / (int)sizeof(Stage)); }
+// Tuning table: the variant of each tile class.  Default: 16x16x4 where both
+// padded edges are multiples of 16, else 4x4x4.
+int32_t g_variant[kClasses] = {0, 0, 0, 0, 0, 1, 0, 1, 0, 0, 0, 0, 0, 1, 0, 1};
 
 // Wavefronts per class for one kernel: the kernel's resident count split in
 // proportion to tiles x padded tile area, multiples of 8 (one share per XCD),
-// at most one wavefront per tile; classes of the other kernel get none.
-ClassWaves class_waves(const NumParams& p, bool big, int resident) {
+// at most one wavefront per tile; classes of other kernels get none.
+ClassWaves class_waves(const NumParams& p, int kid, int resident) {
   ClassWaves cw;
   double wsum = 0.0;
   for (int c = 0; c < kClasses; ++c)
-    if (is_big_class(c) == big) wsum += double(p.cls_tile[c + 1] - p.cls_tile[c]) * ((c / 4 + 1) * (c % 4 + 1));
+    if (kernel_of(c, g_variant[c]) == kid) wsum += double(p.cls_tile[c + 1] - p.cls_tile[c]) * ((c / 4 + 1) * (c % 4 + 1));
   cw.w[0] = 0;
   for (int c = 0; c < kClasses; ++c) {
     const int64_t nt = p.cls_tile[c + 1] - p.cls_tile[c];
     int64_t w = 0;
-    if (nt > 0 && is_big_class(c) == big) {
+    if (nt > 0 && kernel_of(c, g_variant[c]) == kid) {
       const double share = double(nt) * ((c / 4 + 1) * (c % 4 + 1)) / wsum;
       w = std::max<int64_t>(kXcd, ((int64_t)(share * resident) / kXcd) * kXcd);
       w = std::min<int64_t>(w, ((nt + kXcd - 1) / kXcd) * kXcd);
@@ -349,26 +324,39 @@ ClassWaves class_waves(const NumParams& p, bool big, int resident) {
   return cw;
 }
 
-}  // namespace
-
-hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p) {
-  if (p.cls_tile[kClasses] == 0) return hipSuccess;
-  if (!p.desc || p.ncu <= 0) return hipErrorInvalidValue;
-  for (int big = 1; big >= 0; --big) {
-    const ClassWaves cw = class_waves(p, big, p.ncu * waves_per_cu(big ? kWavesBig : kWavesSmall));
+template <bool GEN>
+hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
+  for (int kid = kKernels - 1; kid >= 0; --kid) {
+    const ClassWaves cw = class_waves(p, kid, p.ncu * 4 * kKernWaves[kid]);
     const int W = cw.w[kClasses];
     if (W == 0) continue;
-    if (big) {
-      if (generic) hipLaunchKernelGGL((k_numeric_big<true>), dim3(W), dim3(64), 0, s, p, cw);
-      else hipLaunchKernelGGL((k_numeric_big<false>), dim3(W), dim3(64), 0, s, p, cw);
-    } else {
-      if (generic) hipLaunchKernelGGL((k_numeric_small<true>), dim3(W), dim3(64), 0, s, p, cw);
-      else hipLaunchKernelGGL((k_numeric_small<false>), dim3(W), dim3(64), 0, s, p, cw);
+    switch (kid) {
+      case 0: hipLaunchKernelGGL((k_numeric<GEN, 0>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 1: hipLaunchKernelGGL((k_numeric<GEN, 1>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 2: hipLaunchKernelGGL((k_numeric<GEN, 2>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 3: hipLaunchKernelGGL((k_numeric<GEN, 3>), dim3(W), dim3(64), 0, s, p, cw); break;
+      default: hipLaunchKernelGGL((k_numeric<GEN, 4>), dim3(W), dim3(64), 0, s, p, cw); break;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p) {
+  if (p.cls_tile[kClasses] == 0) return hipSuccess;
+  if (!p.desc || p.ncu <= 0) return hipErrorInvalidValue;
+  return generic ? launch_kernels<true>(s, p) : launch_kernels<false>(s, p);
+}
+
+void get_variants(int32_t* out) { std::copy(g_variant, g_variant + kClasses, out); }
+bool set_variants(const int32_t* in) {
+  for (int c = 0; c < kClasses; ++c)
+    if (in[c] != 0 && in[c] != 1) return false;
+  std::copy(in, in + kClasses, g_variant);
+  return true;
 }
 
 // ----------------------------------------------------- task descriptors

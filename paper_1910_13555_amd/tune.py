@@ -1,0 +1,103 @@
+"""Autotuner of the numeric phase: picks, per output tile class, the
+matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4) that runs a workload
+fastest, by timing the numeric phase on the GPU (coordinate descent over the
+16 classes, starting from the built-in table), and writes the table as JSON
+for bsm_tune_load.
+
+Usage: python -m paper_1910_13555_amd.tune [--workload banded|batched|tall_skinny]
+                                           [--out FILE] [--reps N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNED_DIR = os.path.join(HERE, "tuned")
+
+
+def _runner(name):
+    """A closure that runs the workload's numeric phase once (plans built here)."""
+    import torch
+    import workloads
+    import paper_1910_13555_amd as bsm
+    ctx = bsm.default_context()
+    if name == "batched":
+        probs = workloads.batched()
+        mats = [(bsm.BlockSparseMatrix.from_workload(p["A"], ctx=ctx),
+                 bsm.BlockSparseMatrix.from_workload(p["B"], ctx=ctx)) for p in probs]
+        plans = [bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, None, p["eps"])
+                 for (A, B), p in zip(mats, probs)]
+        batch = bsm.bsm_batch_create(ctx, plans)
+        a = [m[0].values for m in mats]
+        b = [m[1].values for m in mats]
+        outs = batch.execute(1.0, a, b)
+        keep = (mats, plans, batch, outs)
+        return (lambda: batch.execute(1.0, a, b, out=outs)), keep
+    d = {"banded": workloads.banded, "tall_skinny": workloads.tall_skinny}[name]()
+    A = bsm.BlockSparseMatrix.from_workload(d["A"], ctx=ctx)
+    B = bsm.BlockSparseMatrix.from_workload(d["B"], ctx=ctx)
+    Cm = bsm.BlockSparseMatrix.from_workload(d["C"], ctx=ctx) if d["C"] is not None else None
+    plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values,
+                                 Cm.pattern if Cm else None, d["eps"])
+    out = torch.empty(plan.info["c_nvals"], dtype=torch.float64, device="cuda")
+    cin = Cm.values if Cm else None
+    keep = (A, B, Cm, plan, out)
+    return (lambda: plan.execute(d["alpha"], A.values, B.values, d["beta"], cin, out)), keep
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(workload="banded", reps=10, min_gain=0.02):
+    import paper_1910_13555_amd as bsm
+    fn, keep = _runner(workload)
+    bsm.bsm_tune_load(None)
+    table = bsm.bsm_tune_get()
+    best = _time(fn, reps)
+    start = best
+    trials = []
+    for c in range(16):
+        trial = list(table)
+        trial[c] = 1 - trial[c]
+        bsm.bsm_tune_set(trial)
+        t = _time(fn, reps)
+        trials.append({"class": c, "variant": trial[c], "ms": t})
+        if t < best * (1.0 - min_gain):
+            table, best = trial, t
+    bsm.bsm_tune_set(table)
+    del keep
+    return {"workload": workload, "variant": table, "default_ms": start, "tuned_ms": best,
+            "trials": trials}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="banded", choices=["banded", "batched", "tall_skinny"])
+    ap.add_argument("--out", default=None, help="JSON file (default: tuned/<workload>.json here)")
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(HERE))
+    res = tune(args.workload, args.reps)
+    out = args.out or os.path.join(TUNED_DIR, f"{args.workload}.json")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps({k: res[k] for k in ("workload", "variant", "default_ms", "tuned_ms")}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -111,3 +111,28 @@ def test_device_calls_on_host_context_fail_cleanly():
     for h in (A, B):
         _lib.check(_lib.lib.bsm_pattern_destroy(h))
     _lib.check(_lib.lib.bsm_ctx_destroy(ctx))
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    import paper_1910_13555_amd as bsm
+    default = bsm.bsm_tune_get()
+    assert default == [0, 0, 0, 0, 0, 1, 0, 1, 0, 0, 0, 0, 0, 1, 0, 1]
+    try:
+        bsm.bsm_tune_set([1] * 16)
+        assert bsm.bsm_tune_get() == [1] * 16
+        with pytest.raises(bsm.BsmError):
+            bsm.bsm_tune_set([2] + [0] * 15)
+        assert bsm.bsm_tune_get() == [1] * 16      # rejected tables change nothing
+        f = tmp_path / "tune.json"
+        f.write_text('{"workload": "x", "variant": [0, 1, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 1, 1, 1, 1]}')
+        bsm.bsm_tune_load(f)
+        assert bsm.bsm_tune_get() == [0, 1, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 1, 1, 1, 1]
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"variant": [0, 1]}')
+        with pytest.raises(bsm.BsmError):
+            bsm.bsm_tune_load(bad)
+        with pytest.raises(bsm.BsmError):
+            bsm.bsm_tune_load(tmp_path / "missing.json")
+    finally:
+        bsm.bsm_tune_load(None)
+    assert bsm.bsm_tune_get() == default

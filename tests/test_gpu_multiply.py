@@ -147,3 +147,44 @@ def test_banded_full_size_sampled_rows(bsm):
 def test_tall_skinny_full_size_sampled_rows(bsm):
     d = workloads.tall_skinny()
     sampled_rows_check(bsm, d, 10, 1)
+
+
+@pytest.fixture
+def variants(bsm):
+    """Force one matrix-core variant for every tile class, restore the default after."""
+    def force(v):
+        bsm.bsm_tune_set([v] * 16)
+    yield force
+    bsm.bsm_tune_load(None)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_long_stacks_multi_segment(bsm, variants, variant):
+    """About 180 products per output block: tiles span several 64-product
+    segments; blocks of 40 and 47 split into 32 + remainder tiles."""
+    variants(variant)
+    rng = np.random.default_rng(77)
+    ks = rng.choice(np.array([5, 13, 23], np.int32), size=200)
+    rs = np.array([13, 40, 3], np.int32)
+    cs = np.array([23, 7, 47], np.int32)
+    dA = workloads.random_matrix(rng, rs, ks, 0.9)
+    dB = workloads.random_matrix(rng, ks, cs, 0.9)
+    dC = workloads.random_matrix(rng, rs, cs, 0.5)
+    out = check_against_oracle(bsm, dA, dB, dC, 0.5, -1.0)
+    assert out.plan.info["nprod"] > 3 * 64
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("seed", range(8))
+def test_random_cases_forced_variant(bsm, variants, variant, seed):
+    variants(variant)
+    rng = np.random.default_rng(3000 + seed)
+    sizes = [(1, 2, 3, 4), (5, 13, 23), (1, 8, 33, 47), (15, 16, 17, 31, 32)][seed % 4]
+    nbr, nbk, nbc = (int(x) for x in rng.integers(1, 9, 3))
+    dA, dB, dC = workloads.random_case(rng, nbr, nbk, nbc, sizes, 0.5, 0.5, 0.3)
+    ta, tb = bool(seed % 2), bool((seed // 2) % 2)
+    if ta:
+        dA = workloads.random_matrix(rng, dA["col_sizes"], dA["row_sizes"], 0.5)
+    if tb:
+        dB = workloads.random_matrix(rng, dB["col_sizes"], dB["row_sizes"], 0.5)
+    check_against_oracle(bsm, dA, dB, dC, 1.5, 0.5 if dC is not None else 0.0, 0.0, ta, tb)
