@@ -55,7 +55,14 @@ __device__ __forceinline__ TaskDesc desc_at(const NumParams& P, int t) {
 }
 
 // Buffers and scalars of problem pid: the batch table, or the launch's own.
+template <bool BATCH = true>
 __device__ __forceinline__ ProbPtrs prob(const NumParams& P, int pid) {
+  if (!BATCH) {
+    ProbPtrs q;
+    q.out = P.out; q.cin = P.cin; q.X = P.X; q.Y = P.Y; q.px = P.px; q.py = P.py;
+    q.alpha = P.alpha; q.beta = P.beta; q.inplace_skip = P.inplace_skip; q.pad = 0;
+    return q;
+  }
 #if defined(__HIP_DEVICE_COMPILE__)
   if (P.ptab) return cptr(P.ptab)[__builtin_amdgcn_readfirstlane(pid)];
 #else
@@ -65,6 +72,29 @@ __device__ __forceinline__ ProbPtrs prob(const NumParams& P, int pid) {
   q.out = P.out; q.cin = P.cin; q.X = P.X; q.Y = P.Y; q.px = P.px; q.py = P.py;
   q.alpha = P.alpha; q.beta = P.beta; q.inplace_skip = P.inplace_skip; q.pad = 0;
   return q;
+}
+
+// Operand pointers of problem pid (the issue side of the numeric kernels).
+struct OpPtrs {
+  const double* X;
+  const double* Y;
+  const int64_t* px;
+  const int64_t* py;
+};
+template <bool BATCH = true>
+__device__ __forceinline__ OpPtrs op_ptrs(const NumParams& P, int pid) {
+  OpPtrs o;
+  if (BATCH && P.ptab) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int i = __builtin_amdgcn_readfirstlane(pid);
+    o.X = cptr(P.ptab)[i].X; o.Y = cptr(P.ptab)[i].Y; o.px = cptr(P.ptab)[i].px; o.py = cptr(P.ptab)[i].py;
+#else
+    o.X = P.ptab[pid].X; o.Y = P.ptab[pid].Y; o.px = P.ptab[pid].px; o.py = P.ptab[pid].py;  // host pass
+#endif
+  } else {
+    o.X = P.X; o.Y = P.Y; o.px = P.px; o.py = P.py;
+  }
+  return o;
 }
 
 // First work item at or after the fraction i/n of [d0, d1) that starts a tile.

@@ -99,6 +99,7 @@ struct NumParams {
   int32_t ncu = 0;                // compute units (the persistent grids fill them)
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
   int32_t inplace_skip = 0;       // out == cin, beta == 1: blocks without products untouched
+  int32_t has_cin = 0;            // batches: some problem adds beta * C_in
 };
 
 // Product-list construction for the gradient (bsm_backward.hip).

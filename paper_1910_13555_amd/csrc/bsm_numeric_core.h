@@ -1,0 +1,460 @@
+// Numeric phase of the block-sparse multiply (gfx950 / CDNA4).
+//
+// Work item ("task"): one output tile -- at most 32 x 32 elements of one
+// output block C_ij -- with one segment of at most 64 of that block's
+// products (its stack, Sec. 2), accumulated in registers:
+//     C_ij(tile) = beta * C_in + alpha * sum_k A_ik(tile rows) . B_kj(tile cols).
+//
+// Operands go straight from memory into matrix-core operand registers: each
+// lane loads exactly the A and B elements its lane slot of the instruction
+// needs, with no LDS staging, no tables and no barriers.  A "step" is one
+// product's k range [16 j, 16 j + 16): four instruction k-steps of 4 (steps
+// past the product's K are skipped).  Two instruction shapes:
+//   variant 0: FP64 4x4x4 in its 4-block form -- an 8 x 8 output per
+//              instruction, tiles padded to multiples of 8;
+//   variant 1: FP64 16x16x4 -- a 16 x 16 output per instruction, tiles padded
+//              to multiples of 16, half the operand loads per flop.
+// The variant of each tile class (padded rows x columns in {8,16,24,32}^2)
+// comes from the tuning table.
+//
+// The kernels are persistent: wavefronts own contiguous slices of one
+// class's tasks (contiguous per XCD too, so output blocks that share operand
+// blocks are served from one L2), and run them as one software pipeline of
+// depth D: the loads of step s + D are issued as soon as step s has been
+// multiplied, across task boundaries, and each task's product records are
+// fetched one task ahead.  Unused operand slots read a zero in device memory,
+// so every step issues the same number of loads.
+//
+// Every output element has exactly one owner: no atomics, and results are
+// bit-identical from run to run (the GPU counterpart of Sec. 2's static
+// assignment of batches to threads).
+#pragma once
+
+#include "bsm_device.h"
+
+namespace bsm {
+
+// Tuning table: the variant of each tile class (bsm_numeric.hip).
+extern int32_t g_variant[kClasses];
+
+// Target of the loads of padding slots (see above).
+static __device__ double kZeroD = 0.0;
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Buffer resources (base, size in bytes; raw, 32-bit elements format):
+// loads beyond the size return zero and stores beyond it are dropped.
+constexpr uint32_t kOob = 0x80000000u;   // an offset past every block (blocks < 2 GB)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const double* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
+constexpr int KS = 16;   // k per pipeline step
+
+// Kernels: (variant, tile size) combinations, each with its own pipeline
+// depth and register budget (resident wavefronts per SIMD).
+constexpr int kKernels = 5;
+constexpr int kKernVariant[kKernels] = {0, 0, 0, 1, 1};
+constexpr int kKernDepth[kKernels] = {2, 2, 2, 4, 2};
+constexpr int kKernWaves[kKernels] = {4, 3, 2, 4, 3};
+
+// Kernel of class c under variant v: tiles up to 16 x 16, with 24, with 32
+// (variant 0); 16 x 16, larger (variant 1).
+__host__ __device__ constexpr int kernel_of(int c, int v) {
+  return v == 0 ? ((c / 4 == 3 || c % 4 == 3) ? 2 : (c / 4 == 2 || c % 4 == 2) ? 1 : 0)
+                : ((c / 4 < 2 && c % 4 < 2) ? 3 : 4);
+}
+
+struct ClassWaves {
+  int32_t w[kClasses + 1];  // class c's wavefronts: [w[c], w[c+1]) of the grid
+};
+
+// Pipelined loop over this wavefront's tiles of one class; NI x NJ
+// instructions per tile (8 x 8 outputs each for V = 0, 16 x 16 for V = 1).
+// The wavefront owns the tiles whose first work item sits at e0 + r,
+// e0 + r + stride, ... inside [e0, e1), each with the work items that
+// continue it.
+template <int V, int NI, int NJ, bool GEN, bool CIN, bool BATCH, int D>
+__device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, int r, int stride) {
+  const int l = threadIdx.x;
+  // lane roles: rows (A) / columns (B) and instruction k index
+  const int lrA = V == 0 ? 4 * ((l >> 3) & 1) + (l & 3) : (l & 15);   // row inside an instruction tile
+  const int lcB = V == 0 ? 4 * ((l >> 2) & 1) + (l & 3) : (l & 15);   // column inside an instruction tile
+  const int lk = V == 0 ? (l >> 4) : (l >> 4);                        // k inside an instruction k-step
+  constexpr int TI = V == 0 ? 8 : 16;                                  // instruction tile edge
+
+  // ---- issue side: a cursor over (work item, product, k step), kept in
+  // scalar registers and fed by scalar loads issued one product (records)
+  // or one work item (descriptors) ahead, so that the vector memory counter
+  // only ever tracks operand loads and every step issues the same number of
+  // them.
+  int own = e0 + r;                        // own slot of the current tile
+  while (own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
+  if (own >= e1) return;
+  auto rec = [&](const OpPtrs& pp, const TaskDesc& d, int p, int64_t& xw, int64_t& yw)
+                 __attribute__((always_inline)) {
+    xw = cptr(pp.px)[d.pbeg + p];
+    yw = cptr(pp.py)[d.pbeg + p];
+  };
+  // the item after item i (flags f): its tile's next segment, else the next
+  // own slot (checked for a tile start on arrival)
+  auto candidate = [&](int i, int f) __attribute__((always_inline)) {
+    return (f & kTaskLast) ? own + stride : i + 1;
+  };
+  int it = own, ip = 0, ij = 0;
+  TaskDesc id = desc_at(P, it);
+  OpPtrs ipp = op_ptrs<BATCH>(P, id.pid);
+  int nit = candidate(it, id.flags);
+  TaskDesc nd = id;                        // descriptor of item nit (if nit < e1)
+  OpPtrs npp = ipp;
+  if (nit < e1) {
+    nd = desc_at(P, nit);
+    npp = op_ptrs<BATCH>(P, nd.pid);
+  }
+  int64_t cx = 0, cy = 0;                  // record of product ip of item it
+  int64_t nx = 0, ny = 0;                  // record of the product after it
+  if (id.np > 0) rec(ipp, id, 0, cx, cy);
+  bool pending = true;                     // the next record is still to be requested
+  auto request_next = [&]() __attribute__((always_inline)) {
+    if (ip + 1 < id.np) rec(ipp, id, ip + 1, nx, ny);
+    else if (nit < e1 && nd.np > 0) rec(npp, nd, 0, nx, ny);
+  };
+
+  constexpr int NE = V == 0 ? 1 : 4;      // accumulator doubles per instruction tile and lane
+  constexpr bool PRE = CIN && !GEN;        // C_in read with the tile's last operands
+  double A[D][NI][4], B[D][NJ][4];
+  double Cb[D][PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1];
+  int titem[D], tflag[D];                  // per buffer: work item; flags | active k-steps << 2
+
+  auto issue = [&](double (&a)[NI][4], double (&b)[NJ][4], double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1],
+                   int& item, int& flag) __attribute__((always_inline)) {
+    const bool live = it < e1;
+    if (live && pending) {
+      request_next();
+      pending = false;
+    }
+    const bool has = live && id.np > 0;
+    const int64_t xo = (int64_t)((uint64_t)cx & kMask48), yo = (int64_t)((uint64_t)cy & kMask48);
+    const int K = has ? (int)((uint64_t)cx >> 48) : 0;
+    const int q = (int)((uint64_t)cy >> 48);
+    const int k0 = KS * ij;
+    const int kv = has ? min(KS, K - k0) : 0;      // valid k of this step
+    const int r0 = id.tr * kTile, c0 = id.tc * kTile;
+    const int mt = min(kTile, (int)id.M - r0), nt = min(kTile, (int)id.N - c0);
+    if constexpr (GEN) {
+      const int qa = P.mx == kRowSplit ? (int)id.qo : q;
+#pragma unroll
+      for (int x = 0; x < NI; ++x) {
+        const int r = TI * x + lrA;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int kq = 4 * ks + lk;
+          const bool v = r < mt && kq < kv;
+          const int64_t ad = eaddr(P.mx, xo, r0 + r, k0 + kq, id.M, K, qa);
+          a[x][ks] = *(v ? gptr(ipp.X) + ad : gptr(&kZeroD));
+        }
+      }
+#pragma unroll
+      for (int y = 0; y < NJ; ++y) {
+        const int c = TI * y + lcB;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int kq = 4 * ks + lk;
+          const bool v = c < nt && kq < kv;
+          const int64_t ad = eaddr(P.my, yo, k0 + kq, c0 + c, K, id.N, q);
+          b[y][ks] = *(v ? gptr(ipp.Y) + ad : gptr(&kZeroD));
+        }
+      }
+    } else {
+      // Row-major blocks through buffer resources spanning exactly the
+      // product's A and B blocks: reads past a block return zero, so B's
+      // k padding needs no test, and padding lanes read offset kOob.
+      const auto ra = make_rsrc(has ? ipp.X + xo : nullptr, has ? (uint32_t)(id.M * K) * 8u : 0u);
+      const auto rb = make_rsrc(has ? ipp.Y + yo : nullptr, has ? (uint32_t)(K * id.N) * 8u : 0u);
+#pragma unroll
+      for (int x = 0; x < NI; ++x) {
+        const int r = TI * x + lrA;
+        const uint32_t rowk = (uint32_t)((r0 + r) * K + k0 + lk) * 8u;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const bool v = r < mt && 4 * ks + lk < kv;
+          a[x][ks] = buf_load(ra, v ? rowk + 32u * ks : kOob);
+        }
+      }
+#pragma unroll
+      for (int y = 0; y < NJ; ++y) {
+        const int c = TI * y + lcB;
+        const uint32_t colk = c < nt ? (uint32_t)((k0 + lk) * id.N + c0 + c) * 8u : kOob;
+        const uint32_t step = (uint32_t)(4 * id.N) * 8u;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) b[y][ks] = buf_load(rb, colk + step * ks);
+      }
+      if constexpr (PRE) {
+        // the tile's C_in, requested with its last step (every step issues
+        // these loads, out of range unless they are needed)
+        const bool last = live && !(has && k0 + KS < K) && ip + 1 >= id.np && (id.flags & kTaskLast);
+        const ProbPtrs pp = prob<BATCH>(P, id.pid);
+        const bool want = last && pp.beta != 0.0 && id.cin >= 0;
+        const auto rc = make_rsrc(want ? pp.cin + id.cin : nullptr, want ? (uint32_t)(id.M * id.N) * 8u : 0u);
+#pragma unroll
+        for (int x = 0; x < NI; ++x)
+#pragma unroll
+          for (int y = 0; y < NJ; ++y)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+              const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+              const int cc = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+              const uint32_t off = (rr < mt && cc < nt) ? (uint32_t)((r0 + rr) * id.N + c0 + cc) * 8u : kOob;
+              cb[x][y][e] = buf_load(rc, off);
+            }
+      }
+    }
+    item = it;
+    flag = live ? 1 | (((kv + 3) / 4) << 2) : 0;
+    if (!live) return;
+    // advance the cursor
+    if (has && k0 + KS < K) {
+      ++ij;
+      return;
+    }
+    ij = 0;
+    if (++ip < id.np) {                    // next product of the same item
+      cx = nx;
+      cy = ny;
+      pending = true;
+      return;
+    }
+    if (id.flags & kTaskLast) flag |= 2;   // the tile's last step: write it out
+    const bool new_tile = (id.flags & kTaskLast) != 0;
+    ip = 0;
+    it = nit;
+    if (it >= e1) return;
+    if (new_tile) {
+      own = it;
+      if (!(nd.flags & kTaskFirst)) {      // own slot inside another tile: skip ahead
+        while (own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
+        it = own;
+        if (it >= e1) return;
+        nd = desc_at(P, it);
+        npp = op_ptrs<BATCH>(P, nd.pid);
+        if (nd.np > 0) rec(npp, nd, 0, nx, ny);
+      }
+    }
+    id = nd;
+    ipp = npp;
+    cx = nx;
+    cy = ny;
+    nit = candidate(it, id.flags);
+    if (nit < e1) {
+      nd = desc_at(P, nit);
+      npp = op_ptrs<BATCH>(P, nd.pid);
+    }
+    pending = true;
+  };
+
+  // ---- compute side
+  using Acc = typename std::conditional<V == 0, double, f64x4>::type;
+  Acc acc[NI][NJ];
+#pragma unroll
+  for (int x = 0; x < NI; ++x)
+#pragma unroll
+    for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
+  auto epilogue = [&](const TaskDesc& d, const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1])
+                      __attribute__((always_inline)) {
+    const int r0 = d.tr * kTile, c0 = d.tc * kTile;
+    const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
+    const ProbPtrs pp = prob<BATCH>(P, d.pid);
+    const bool use_cin = pp.beta != 0.0 && d.cin >= 0;
+    const bool write = !(pp.inplace_skip && d.np == 0);
+    if constexpr (!GEN) {
+      if (write) {
+        // stores past the output block (padding lanes: offset kOob) are dropped
+        const auto ro = make_rsrc(pp.out + d.cout, (uint32_t)(d.M * d.N) * 8u);
+#pragma unroll
+        for (int x = 0; x < NI; ++x)
+#pragma unroll
+          for (int y = 0; y < NJ; ++y)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+              // variant 0: lane j + 4b + 16i holds (4(b/2) + i, 4(b%2) + j) of
+              // the 8 x 8 tile; variant 1: element e of lane l is (4e + l/16, l%16)
+              const int r = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+              const int c = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+              double av;
+              if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
+              const uint32_t off = (r < mt && c < nt) ? (uint32_t)((r0 + r) * d.N + c0 + c) * 8u : kOob;
+              double v = pp.alpha * av;
+              if constexpr (PRE) {
+                if (use_cin) v += pp.beta * cb[x][y][e];
+              }
+              buf_store(ro, off, v);
+            }
+      }
+    } else {
+#pragma unroll
+      for (int x = 0; x < NI; ++x)
+#pragma unroll
+        for (int y = 0; y < NJ; ++y)
+#pragma unroll
+          for (int e = 0; e < NE; ++e) {
+            const int r = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+            const int c = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+            double av;
+            if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
+            if (write && r < mt && c < nt) {
+              const int64_t rel = eaddr(P.mo, 0, r0 + r, c0 + c, d.M, d.N, d.qo);
+              double v = pp.alpha * av;
+              if (use_cin) v += pp.beta * gptr(pp.cin)[d.cin + rel];
+              gptr(pp.out)[d.cout + rel] = v;
+            }
+          }
+    }
+#pragma unroll
+    for (int x = 0; x < NI; ++x)
+#pragma unroll
+      for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
+  };
+  auto compute = [&](const double (&a)[NI][4], const double (&b)[NJ][4], int nks) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (ks < nks) {
+#pragma unroll
+        for (int x = 0; x < NI; ++x)
+#pragma unroll
+          for (int y = 0; y < NJ; ++y) {
+            if constexpr (V == 0)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+            else
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+          }
+      }
+    }
+  };
+
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue(A[d], B[d], Cb[d], titem[d], tflag[d]);
+  // steady state; the first empty buffer ends the wavefront's work (leaving
+  // straight out of the loop keeps every path through it issuing the same
+  // loads, so the compiler can count them exactly)
+  while (true) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (!(tflag[d] & 1)) return;
+      compute(A[d], B[d], tflag[d] >> 2);
+      if (tflag[d] & 2) epilogue(desc_at(P, titem[d]), Cb[d]);
+      issue(A[d], B[d], Cb[d], titem[d], tflag[d]);
+    }
+  }
+}
+
+// Persistent kernel KID.  Wavefronts [W.w[c], W.w[c+1]) serve class c (a
+// multiple of 8 of them).  Workgroups are dealt to the 8 XCDs round-robin, so
+// local wavefront w runs on XCD w % 8; each XCD owns one contiguous eighth of
+// the class's work items (cut at tile starts), and its wavefronts take that
+// eighth's tiles cyclically.  All wavefronts of an XCD therefore work on
+// neighbouring output blocks at any moment, and the operand blocks those
+// share stay in the XCD's L2.
+template <bool GEN, bool CIN, bool BATCH, int KID>
+__device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* cls_wave) {
+  const int b = blockIdx.x;
+  int c = 0;
+  while (c < kClasses - 1 && b >= cls_wave[c + 1]) ++c;
+  const int n = cls_wave[c + 1] - cls_wave[c];
+  const int w = b - cls_wave[c];
+  const int x = w % kXcd, r = w / kXcd;
+  const int64_t d0 = P.seg ? P.seg[P.cls_tile[c]] : P.cls_tile[c];
+  const int64_t d1 = P.seg ? P.seg[P.cls_tile[c + 1]] : P.cls_tile[c + 1];
+  const int e0 = slice_start(P.desc, d0, d1, x, kXcd), e1 = slice_start(P.desc, d0, d1, x + 1, kXcd);
+  if (e0 + r >= e1) return;
+  constexpr int V = kKernVariant[KID];
+  constexpr int DP = kKernDepth[KID];
+  // one call per distinct instruction grid of this kernel's classes
+  const int ni = V == 0 ? c / 4 + 1 : (c / 4 + 2) / 2;
+  const int nj = V == 0 ? c % 4 + 1 : (c % 4 + 2) / 2;
+  switch (ni * 8 + nj) {
+#define BSM_SHAPE(NI_, NJ_)                                                              \
+  case NI_ * 8 + NJ_:                                                                    \
+    if constexpr (V == 0 ? kernel_of((NI_ - 1) * 4 + NJ_ - 1, 0) == KID                  \
+                         : kernel_of((2 * NI_ - 1) * 4 + 2 * NJ_ - 1, 1) == KID)         \
+      run_tiles<V, NI_, NJ_, GEN, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd);                \
+    break;
+    BSM_SHAPE(1, 1) BSM_SHAPE(1, 2) BSM_SHAPE(1, 3) BSM_SHAPE(1, 4)
+    BSM_SHAPE(2, 1) BSM_SHAPE(2, 2) BSM_SHAPE(2, 3) BSM_SHAPE(2, 4)
+    BSM_SHAPE(3, 1) BSM_SHAPE(3, 2) BSM_SHAPE(3, 3) BSM_SHAPE(3, 4)
+    BSM_SHAPE(4, 1) BSM_SHAPE(4, 2) BSM_SHAPE(4, 3) BSM_SHAPE(4, 4)
+#undef BSM_SHAPE
+  }
+}
+
+}  // namespace
+
+// CIN: some tile adds beta * C_in (read ahead with the operands on the
+// row-major path, so that the epilogue never waits on memory).  BATCH: the
+// buffers and scalars come from the per-problem table.
+template <bool GEN, bool CIN, bool BATCH, int KID>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kKernWaves[KID])))
+k_numeric(NumParams P, ClassWaves W) {
+  numeric_body<GEN, CIN, BATCH, KID>(P, W.w);
+}
+
+namespace {
+
+
+// Wavefronts per class for one kernel: the kernel's resident count split in
+// proportion to tiles x padded tile area, multiples of 8 (one share per XCD),
+// at most one wavefront per tile; classes of other kernels get none.
+ClassWaves class_waves(const NumParams& p, int kid, int resident) {
+  ClassWaves cw;
+  double wsum = 0.0;
+  for (int c = 0; c < kClasses; ++c)
+    if (kernel_of(c, g_variant[c]) == kid) wsum += double(p.cls_tile[c + 1] - p.cls_tile[c]) * ((c / 4 + 1) * (c % 4 + 1));
+  cw.w[0] = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    const int64_t nt = p.cls_tile[c + 1] - p.cls_tile[c];
+    int64_t w = 0;
+    if (nt > 0 && kernel_of(c, g_variant[c]) == kid) {
+      const double share = double(nt) * ((c / 4 + 1) * (c % 4 + 1)) / wsum;
+      w = std::max<int64_t>(kXcd, ((int64_t)(share * resident) / kXcd) * kXcd);
+      w = std::min<int64_t>(w, ((nt + kXcd - 1) / kXcd) * kXcd);
+    }
+    cw.w[c + 1] = (int32_t)(cw.w[c] + w);
+  }
+  return cw;
+}
+
+template <bool GEN, bool CIN, bool BATCH>
+hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
+  for (int kid = kKernels - 1; kid >= 0; --kid) {
+    const ClassWaves cw = class_waves(p, kid, p.ncu * 4 * kKernWaves[kid]);
+    const int W = cw.w[kClasses];
+    if (W == 0) continue;
+    switch (kid) {
+      case 0: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 0>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 1: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 1>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 2: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 2>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 3: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 3>), dim3(W), dim3(64), 0, s, p, cw); break;
+      default: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 4>), dim3(W), dim3(64), 0, s, p, cw); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// Launchers of the kernel families, one translation unit each.
+hipError_t launch_numeric_rm(hipStream_t s, const NumParams& p, bool cin);        // bsm_numeric_rm.hip
+hipError_t launch_numeric_rm_batch(hipStream_t s, const NumParams& p, bool cin);  // bsm_numeric_rmb.hip
+hipError_t launch_numeric_gen(hipStream_t s, const NumParams& p, bool batch);     // bsm_numeric_gen.hip
+
+}  // namespace bsm
