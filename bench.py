@@ -3,12 +3,15 @@
 One step = one full multiply C = A.B of the banded workload (2000 x 2000
 blocks of sizes {5,13,23}, band probability 0.5*exp(-|i-j|/40), values
 N(0,1)*exp(-|i-j|/20), filter eps 1e-8): block norms, symbolic phase with the
-single size readback, and the numeric kernel.  Inputs are resident in HBM
+single size readback, and the numeric kernels.  Inputs are resident in HBM
 before timing starts.  Prints one JSON line, which also carries the
-split-precision forms on the same workload and the 64-problem batch (FP64 and
-bf16x3, replayed from a HIP graph), each with its error against FP64.
+roofline of the dominant numeric kernel (timed live with HIP events on the
+library's stream), the split-precision forms on the same workload and the
+64-problem batch (FP64 and bf16x3, replayed from a HIP graph), each with its
+error against FP64, and the CPU oracle's rate on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+       python bench.py --traffic-from FETCH_CSV WRITE_CSV --copy-bytes N
 """
 from __future__ import annotations
 
@@ -25,18 +28,23 @@ sys.path.insert(0, ROOT)
 METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B; % FP64 roofline; split vs FP64"
 PEAK_FP64 = 78.6e12       # MI355X dense FP64 (vector and matrix core), FLOP/s
 PEAK_HBM = 8.0e12         # MI355X HBM3E, B/s
-KERNELS_SRC = os.path.join(ROOT, "paper_1910_13555_amd", "csrc", "bsm_numeric.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1910_13555_amd", "csrc", "bsm_numeric_core.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_traffic_banded.json")
+TUNED = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "banded.json")
+# numeric kernel families (bsm_ctx_launch_times order) and their names in profiler output
+FAMILIES = ["FP64 4x4x4, tiles <= 16 wide", "FP64 4x4x4, 24 wide", "FP64 4x4x4, 32 wide",
+            "FP64 16x16x4, 16 x 16", "FP64 16x16x4, 32 wide"]
+KERNEL_NAME = "bsm::k_numeric<false, false, false, {}>"
 
 
 def kernel_source_hash() -> str:
-    with open(KERNELS_SRC, "rb") as f:
+    with open(KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per numeric launch from the committed rocprofv3 counter runs,
-    or None if the kernel source changed since they were taken."""
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs, or None if the kernel source changed since they were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -44,7 +52,39 @@ def recorded_traffic():
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_per_launch", {}).get(kernel)
+
+
+def kernel_of(c, v):
+    """Kernel family of tile class c under variant v (mirrors the library's table)."""
+    if v == 0:
+        return 2 if (c // 4 == 3 or c % 4 == 3) else (1 if (c // 4 == 2 or c % 4 == 2) else 0)
+    return 3 if (c // 4 < 2 and c % 4 < 2) else 4
+
+
+def family_flops(plan, A, B, variants):
+    """Useful flops of each numeric kernel family: 2*mt*nt*K per product and
+    output tile (tiles of at most 32 x 32; class from the padded tile shape)."""
+    import numpy as np
+    a, b, c = plan.export_stack()
+    _, ac, _ = A.pattern.export()
+    cr, cc, _ = plan.c_pattern().export()
+    rs = np.asarray(A.row_sizes, np.int64)
+    ks = np.asarray(A.col_sizes, np.int64)
+    cs = np.asarray(B.col_sizes, np.int64)
+    M, N, K = rs[cr[c]], cs[cc[c]], ks[ac[a]]
+    fam_of_cls = np.array([kernel_of(k, int(variants[k])) for k in range(16)])
+    out = np.zeros(5)
+    if len(M) == 0:
+        return out
+    for tr in range(int((M.max() + 31) // 32)):
+        mt = np.clip(M - 32 * tr, 0, 32)
+        for tc in range(int((N.max() + 31) // 32)):
+            nt = np.clip(N - 32 * tc, 0, 32)
+            ok = (mt > 0) & (nt > 0)
+            cls = ((mt[ok] + 7) // 8 - 1) * 4 + (nt[ok] + 7) // 8 - 1
+            np.add.at(out, fam_of_cls[cls], 2.0 * mt[ok] * nt[ok] * K[ok])
+    return out
 
 
 def compulsory_bytes(plan, A, B, beta):
@@ -55,12 +95,11 @@ def compulsory_bytes(plan, A, B, beta):
     _, _, boff = B.pattern.export()
     alen = np.diff(np.append(aoff, A.pattern.nvals))
     blen = np.diff(np.append(boff, B.pattern.nvals))
-    by = 8 * (int(alen[np.unique(a)].sum()) + int(blen[np.unique(b)].sum()) + plan.info["c_nvals"])
-    return by
+    return 8 * (int(alen[np.unique(a)].sum()) + int(blen[np.unique(b)].sum()) + plan.info["c_nvals"])
 
 
-def cpu_baseline(d, nrows=500):
-    """The CPU oracle timed on a bounded sample: every 4th output block row."""
+def cpu_baseline(d, nrows=2000):
+    """The CPU oracle timed on a bounded sample of output block rows (all 2000 by default)."""
     from threadpoolctl import threadpool_limits
     from oracle import blocksparse as ob
     A = ob.BlockSparse.from_workload(d["A"])
@@ -78,8 +117,8 @@ def cpu_baseline(d, nrows=500):
                       f"1 thread, {dt:.1f} s"}
 
 
-def traffic_from_counters(fetch_csv, write_csv, copy_bytes, kernel_prefix):
-    """HBM bytes per launch of the numeric kernel from two rocprofv3 --pmc runs
+def traffic_from_counters(fetch_csv, write_csv, copy_bytes):
+    """HBM bytes per launch of each numeric kernel from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
     counter read for the plain copy of copy_bytes in the same run.  Writes the
     result next to the committed profiles, keyed by the kernel source hash."""
@@ -92,24 +131,24 @@ def traffic_from_counters(fetch_csv, write_csv, copy_bytes, kernel_prefix):
             for row in csv.DictReader(f):
                 if row.get("Counter_Name") == counter:
                     vals[row["Kernel_Name"]].append(float(row["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in vals.items()}
+        return vals
 
-    out = {}
+    rec = {"kernel_source_sha256_16": kernel_source_hash(), "copy_bytes": copy_bytes,
+           "counters": {}, "hbm_bytes_per_launch": {}}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         pk = per_kernel(path, counter)
-        copies = [v for k, v in pk.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-        mine = [v for k, v in pk.items() if k.startswith(kernel_prefix) or kernel_prefix in k]
-        if not copies or not mine:
-            raise SystemExit(f"{path}: no copy or numeric kernel rows for {counter}")
-        factor = copy_bytes / (max(copies) * 1024.0)
-        out[counter] = {"kib_per_dispatch": mine[0], "copy_kib": max(copies), "scale": factor,
-                        "bytes_per_launch": mine[0] * 1024.0 * factor}
-    rec = {"kernel": kernel_prefix, "kernel_source_sha256_16": kernel_source_hash(),
-           "copy_bytes": copy_bytes, "counters": out,
-           "hbm_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]}
+        # the runtime's device copy kernel; the largest dispatch is the calibration copy
+        copies = [max(v) for k, v in pk.items() if "copyBuffer" in k]
+        if not copies:
+            raise SystemExit(f"{path}: no copy kernel rows for {counter}")
+        scale = copy_bytes / (max(copies) * 1024.0)
+        mine = {k.split("(")[0].replace("void ", ""): sum(v) / len(v) for k, v in pk.items() if "k_numeric" in k}
+        rec["counters"][counter] = {"copy_kib": max(copies), "scale": scale, "kib_per_dispatch": mine}
+        for k, v in mine.items():
+            rec["hbm_bytes_per_launch"][k] = rec["hbm_bytes_per_launch"].get(k, 0.0) + v * 1024.0 * scale
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
-    print(json.dumps(rec))
+    print(json.dumps(rec["hbm_bytes_per_launch"]))
 
 
 def rel_err(x, ref):
@@ -131,6 +170,30 @@ def time_events(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
+def roofline_section(bsm, ctx, plan, A, B, out, reps):
+    """Dominant numeric kernel: its useful flops per launch over its launch
+    time, both measured here (HIP events recorded by the library around each
+    of its launches, on its stream)."""
+    import numpy as np
+    flops = family_flops(plan, A, B, bsm.bsm_tune_get())
+    ctx.set_timing(True)
+    times = np.zeros(5)
+    for _ in range(reps):
+        plan.execute(1.0, A.values, B.values, 0.0, None, out)
+        times += np.asarray(ctx.launch_times())
+    ctx.set_timing(False)
+    times /= reps
+    k = int(np.argmax(times))
+    achieved = flops[k] / (times[k] * 1e-3)
+    name = KERNEL_NAME.format(k)
+    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64, "traffic": recorded_traffic(name),
+            "kernel": name, "family": FAMILIES[k], "launch_ms": float(times[k]),
+            "algorithmic_flops_per_launch": float(flops[k]),
+            "families_ms": [round(float(t), 4) for t in times],
+            "families_gflop": [round(float(f) / 1e9, 4) for f in flops]}
+
+
 def split_section(bsm, ctx, A, B, eps, ref, reps, stream):
     """Split-precision numeric phase on the same workload: rate and error vs the FP64 result."""
     import torch
@@ -148,8 +211,8 @@ def split_section(bsm, ctx, A, B, eps, ref, reps, stream):
 
 
 def batched_section(bsm, reps, stream):
-    """The 64-problem batch: one merged launch replayed from a HIP graph, in
-    FP64 and again in bf16x3 (error vs the FP64 batch)."""
+    """The 64-problem batch: one merged launch per kernel family replayed from
+    a HIP graph, in FP64 and again in bf16x3 (error vs the FP64 batch)."""
     import torch
     import workloads
     probs = workloads.batched()
@@ -203,11 +266,10 @@ def main():
                          "(calibrates HBM byte counters of a profiler run)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no benchmark: turn two rocprofv3 counter CSVs (taken with --copy-bytes) "
-                         "into the recorded HBM traffic of the numeric kernel")
+                         "into the recorded HBM traffic of the numeric kernels")
     args = ap.parse_args()
     if args.traffic_from:
-        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_bytes,
-                              "void bsm::k_numeric<false, 0>")
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_bytes)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -219,9 +281,8 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    tuned = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "banded.json")
-    if os.path.exists(tuned):
-        bsm.bsm_tune_load(tuned)          # tile-class variants chosen by the autotuner
+    if os.path.exists(TUNED):
+        bsm.bsm_tune_load(TUNED)          # tile-class variants chosen by the autotuner
     dev = torch.device("cuda:0")
     d = workloads.banded()
     A = bsm.BlockSparseMatrix.from_workload(d["A"])
@@ -263,21 +324,15 @@ def main():
     numeric_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
     plan = plans[-1]
     info = plan.info
-    plans = plans[:1]
+    del plans
 
-    # numeric-only rate (plan reuse, as in repeated multiplies with a fixed pattern)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.execute(1.0, A.values, B.values, 0.0, None, out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    reuse_ms = e0.elapsed_time(e1) / args.steps
+    # numeric phase alone (plan reuse, as in repeated multiplies with a fixed pattern)
+    reuse_ms = time_events(lambda: plan.execute(1.0, A.values, B.values, 0.0, None, out), args.steps,
+                           stream)
 
     F = info["flops"]
     Bytes = compulsory_bytes(plan, A, B, 0.0)
     t_roof = max(F / PEAK_FP64, Bytes / PEAK_HBM)
-    achieved = F / (numeric_ms * 1e-3)
     res = {
         "metric": METRIC,
         "value": F / (ms_step * 1e-3) / 1e9,
@@ -300,15 +355,12 @@ def main():
         "t_roof_ms": t_roof * 1e3,
         "numeric_ms": numeric_ms,
         "numeric_only_gflops": F / (reuse_ms * 1e-3) / 1e9,
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                     "traffic": recorded_traffic(),
-                     "kernel": "k_numeric_small (FP64 4x4x4 matrix-core tiles; every tile of this "
-                               "workload is at most 24 x 24)"},
+        "roofline": roofline_section(bsm, ctx, plan, A, B, out, args.steps),
+        "tuning": bsm.bsm_tune_get(),
     }
     if not args.no_extra:
         res["split"] = split_section(bsm, ctx, A, B, eps, out, args.steps, stream)
-        del plans, plan, out
+        del plan, out
         torch.cuda.empty_cache()
         res["batched"] = batched_section(bsm, max(2, args.steps // 4), stream)
     if not args.no_cpu:

@@ -88,6 +88,16 @@ bsm_status bsm_ctx_set_stream(bsm_ctx ctx, void* stream);
 /* Wait for the context's stream; reports asynchronous device errors. */
 bsm_status bsm_sync(bsm_ctx ctx);
 bsm_status bsm_ctx_destroy(bsm_ctx ctx);
+/* Launch timing of the FP64 numeric kernels, for measurement: with on != 0,
+ * each bsm_plan_execute on this context records HIP events on the context's
+ * stream around each of its numeric kernel launches (five kernel families:
+ * 0-2 = FP64 4x4x4 tiles up to 16 wide / 24 wide / 32 wide, 3-4 = FP64
+ * 16x16x4 tiles 16 wide / 32 wide).  bsm_ctx_launch_times waits for those
+ * events of the last execute and writes ms_out[5] (host array; 0 for families
+ * that did not run).  BSM_E_INVALID if timing is off, BSM_E_DEVICE on a
+ * host-only context. */
+bsm_status bsm_ctx_set_timing(bsm_ctx ctx, int32_t on);
+bsm_status bsm_ctx_launch_times(bsm_ctx ctx, float* ms_out);
 
 /* ------------------------------------------------------------ patterns
  * Blocked CSR index of a matrix (Sec. 2).  All arrays are host arrays.

@@ -78,6 +78,16 @@ class Context:
     def sync(self):
         check(lib.bsm_sync(self.handle))
 
+    def set_timing(self, on: bool):
+        """Record HIP events around each numeric kernel launch of later executes."""
+        check(lib.bsm_ctx_set_timing(self.handle, int(bool(on))))
+
+    def launch_times(self):
+        """Milliseconds of each numeric kernel family in the last execute (5 floats)."""
+        out = (C.c_float * 5)()
+        check(lib.bsm_ctx_launch_times(self.handle, out))
+        return list(out)
+
     def close(self):
         if self.handle:
             check(lib.bsm_ctx_destroy(self.handle))

@@ -83,6 +83,8 @@ PROTOTYPES = {
     "bsm_contract_plan": [_vp, C.c_char_p, _vp, _dp, _vp, _dp, _vp, C.c_double,
                           C.POINTER(MmOpts), C.POINTER(_vp)],
     "bsm_plan_t3_pattern": [_vp, C.POINTER(_vp)],
+    "bsm_ctx_set_timing": [_vp, C.c_int32],
+    "bsm_ctx_launch_times": [_vp, C.POINTER(C.c_float)],
     "bsm_tune_load": [C.c_char_p],
     "bsm_tune_get": [_i32p],
     "bsm_tune_set": [_i32p],

@@ -197,6 +197,11 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   P.seg = pl->seg.p;
   std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
+  if (pl->ctx->timing) {
+    std::fill(pl->ctx->launched, pl->ctx->launched + kNumericKernels, 0);
+    P.ev = pl->ctx->ev;
+    P.launched = pl->ctx->launched;
+  }
   if (pl->opts.precision == BSM_PREC_FP64) hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
   else hip_check(launch_numeric_split(pl->ctx->stream, split_pieces(pl->opts.precision), P), "split numeric");
 }
@@ -387,6 +392,33 @@ bsm_status bsm_sync(bsm_ctx ctx) {
     set_device(ctx);
     hip_check(hipStreamSynchronize(ctx->stream), "stream sync");
     hip_check(hipGetLastError(), "async error");
+  });
+}
+
+bsm_status bsm_ctx_set_timing(bsm_ctx ctx, int32_t on) {
+  return guard([&] {
+    if (!ctx) fail(BSM_E_INVALID, "NULL context");
+    if (ctx->device < 0) fail(BSM_E_DEVICE, "host-only context");
+    set_device(ctx);
+    if (on)
+      for (hipEvent_t& e : ctx->ev)
+        if (!e) hip_check(hipEventCreate(&e), "event");
+    std::fill(ctx->launched, ctx->launched + kNumericKernels, 0);
+    ctx->timing = on != 0;
+  });
+}
+
+bsm_status bsm_ctx_launch_times(bsm_ctx ctx, float* ms_out) {
+  return guard([&] {
+    if (!ctx || !ms_out) fail(BSM_E_INVALID, "NULL argument");
+    if (!ctx->timing) fail(BSM_E_INVALID, "timing is off (bsm_ctx_set_timing)");
+    set_device(ctx);
+    for (int k = 0; k < kNumericKernels; ++k) {
+      ms_out[k] = 0.0f;
+      if (!ctx->launched[k]) continue;
+      hip_check(hipEventSynchronize(ctx->ev[2 * k + 1]), "event sync");
+      hip_check(hipEventElapsedTime(&ms_out[k], ctx->ev[2 * k], ctx->ev[2 * k + 1]), "elapsed time");
+    }
   });
 }
 

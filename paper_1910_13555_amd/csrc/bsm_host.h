@@ -129,6 +129,14 @@ struct bsm_ctx_s {
   int refs = 1;  // the creator's reference plus one per live pattern / plan / batch
   int ncu = 0;            // compute units of the device
   Allocator mem;
+  // launch timing of the numeric kernels (bsm_ctx_set_timing)
+  bool timing = false;
+  hipEvent_t ev[2 * bsm::kNumericKernels] = {};
+  int32_t launched[bsm::kNumericKernels] = {};
+  ~bsm_ctx_s() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace bsm_host {

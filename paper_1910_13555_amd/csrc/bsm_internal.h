@@ -100,7 +100,10 @@ struct NumParams {
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
   int32_t inplace_skip = 0;       // out == cin, beta == 1: blocks without products untouched
   int32_t has_cin = 0;            // batches: some problem adds beta * C_in
+  hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
+  int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran
 };
+constexpr int kNumericKernels = 5;  // FP64 numeric kernel families (4x4x4: <=16, 24, 32 wide; 16x16x4: 16, 32)
 
 // Product-list construction for the gradient (bsm_backward.hip).
 struct BwdParams {

@@ -62,7 +62,7 @@ constexpr int KS = 16;   // k per pipeline step
 
 // Kernels: (variant, tile size) combinations, each with its own pipeline
 // depth and register budget (resident wavefronts per SIMD).
-constexpr int kKernels = 5;
+constexpr int kKernels = kNumericKernels;
 constexpr int kKernVariant[kKernels] = {0, 0, 0, 1, 1};
 constexpr int kKernDepth[kKernels] = {2, 2, 2, 4, 2};
 constexpr int kKernWaves[kKernels] = {4, 3, 2, 4, 3};
@@ -437,6 +437,10 @@ hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
     const ClassWaves cw = class_waves(p, kid, p.ncu * 4 * kKernWaves[kid]);
     const int W = cw.w[kClasses];
     if (W == 0) continue;
+    if (p.ev) {
+      const hipError_t e = hipEventRecord(p.ev[2 * kid], s);
+      if (e != hipSuccess) return e;
+    }
     switch (kid) {
       case 0: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 0>), dim3(W), dim3(64), 0, s, p, cw); break;
       case 1: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 1>), dim3(W), dim3(64), 0, s, p, cw); break;
@@ -444,8 +448,13 @@ hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
       case 3: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 3>), dim3(W), dim3(64), 0, s, p, cw); break;
       default: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 4>), dim3(W), dim3(64), 0, s, p, cw); break;
     }
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (p.ev) {
+      e = hipEventRecord(p.ev[2 * kid + 1], s);
+      if (e != hipSuccess) return e;
+      p.launched[kid] = 1;
+    }
   }
   return hipSuccess;
 }
