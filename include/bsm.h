@@ -275,9 +275,17 @@ bsm_status bsm_plan_t3_pattern(bsm_plan plan, bsm_tpattern* out);
  * launch; the autotuner (paper_1910_13555_amd/tune.py) measures both per
  * class and writes a JSON file {"variant": [16 integers], ...}.
  * bsm_tune_load(path) reads such a file (BSM_E_INVALID if unreadable or
- * malformed); path NULL restores the built-in default (16x16x4 where both
- * padded edges are multiples of 16). */
+ * malformed); path NULL restores the built-in defaults (16x16x4 where both
+ * padded edges are multiples of 16; 32 x 32 panels). */
 bsm_status bsm_tune_load(const char* path);
+/* Work order of the numeric phase: output tiles of a class are visited in
+ * panels of rows x cols output blocks (panels row by row, canonical order
+ * inside), so that the wavefronts of an XCD share the A and B blocks of one
+ * panel in L2.  rows = cols = 0 keeps the canonical order; default 32 x 32.
+ * Applies to plans created afterwards; BSM_E_INVALID for negative sizes or one
+ * size 0.  bsm_tune_load also reads an optional "panel": [rows, cols]. */
+bsm_status bsm_tune_panel(int32_t rows, int32_t cols);
+bsm_status bsm_tune_get_panel(int32_t* rows, int32_t* cols);
 /* Current table: out16[c] = variant of class c (host array of 16). */
 bsm_status bsm_tune_get(int32_t* out16);
 /* Replace the table (host array of 16 values in {0, 1}; else BSM_E_INVALID).

@@ -26,7 +26,8 @@ from ._lib import BsmError, MmOpts, PlanInfo, check, lib
 __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmul",
            "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
            "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
-           "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load"]
+           "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load",
+           "bsm_tune_panel", "bsm_tune_get_panel"]
 
 
 _live = {"batch": weakref.WeakSet(), "plan": weakref.WeakSet(), "pattern": weakref.WeakSet(),
@@ -348,6 +349,17 @@ def bsm_tune_set(variants):
     if arr.shape != (16,):
         raise ValueError("16 variants expected")
     check(lib.bsm_tune_set(_lib.as_i32p(arr)))
+
+
+def bsm_tune_panel(rows, cols):
+    """Output panel (block rows x block columns) of the numeric work order; (0, 0): canonical."""
+    check(lib.bsm_tune_panel(int(rows), int(cols)))
+
+
+def bsm_tune_get_panel():
+    r, c = np.zeros(1, np.int32), np.zeros(1, np.int32)
+    check(lib.bsm_tune_get_panel(_lib.as_i32p(r), _lib.as_i32p(c)))
+    return int(r[0]), int(c[0])
 
 
 def bsm_tune_load(path=None):

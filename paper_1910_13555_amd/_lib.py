@@ -86,6 +86,8 @@ PROTOTYPES = {
     "bsm_ctx_set_timing": [_vp, C.c_int32],
     "bsm_ctx_launch_times": [_vp, C.POINTER(C.c_float)],
     "bsm_tune_load": [C.c_char_p],
+    "bsm_tune_panel": [C.c_int32, C.c_int32],
+    "bsm_tune_get_panel": [_i32p, _i32p],
     "bsm_tune_get": [_i32p],
     "bsm_tune_set": [_i32p],
 }

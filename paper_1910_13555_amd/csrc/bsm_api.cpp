@@ -17,6 +17,8 @@ namespace bsm_host {
 
 extern const bsm_mm_opts kDefaultOpts;
 const bsm_mm_opts kDefaultOpts = {0, 0, 0, BSM_PREC_FP64};
+// Output panel (block rows x block columns) of the numeric work order; 0: canonical order.
+int32_t g_panel[2] = {32, 32};
 
 // Work items of the numeric kernel from a tile list: one per (tile, segment
 // of <= 64 products), written on the device; `seg` ends with their count.
@@ -143,9 +145,34 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                             pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p),
             "symbolic fill");
   pl->c_same_as_cin = C && pl->c_nblk == C->nblk;
+  if (g_panel[0] > 0 && pl->ntasks > 1) {
+    const int64_t sb = panel_order_scratch_bytes(pl->ntasks);
+    DBuf<char> sc(ctx, sb);
+    // at most 2^22 panels per direction (the sort key's fields)
+    const int32_t pr = std::max<int32_t>(g_panel[0], (int32_t)((pl->nr + (1 << 22) - 1) >> 22));
+    const int32_t pc = std::max<int32_t>(g_panel[1], (int32_t)((pl->nc + (1 << 22) - 1) >> 22));
+    hip_check(launch_panel_order(st, (int32_t)pl->ntasks, pl->tasks.p, pl->c_row.p, pl->c_col.p, pl->c_rs,
+                                 pl->c_cs, pr, pc, sc.p, sb),
+              "panel order");
+  }
   build_desc(ctx, pl->ntasks, pl->tasks.p, pl->c_row.p, pl->c_col.p, pl->c_off.p, pl->cin_off.p,
              pl->pptr.p, pl->c_rs, pl->c_cs, pl->rowq.p, pl->nprod,
              max_tiles(ta ? A->h_cs : A->h_rs, tb ? B->h_rs : B->h_cs), pl->seg, pl->desc);
+  if (pl->step_path() && pl->ntasks > 0) {
+    // step records: per-tile counts, scan, fill (the total is read back once)
+    DBuf<int64_t> ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1), tot1(ctx, 1);
+    hip_check(launch_count_steps(st, (int32_t)pl->ntasks, pl->tasks.p, pl->pptr.p, pl->px.p, ns.p), "step count");
+    DBuf<int64_t> scr2(ctx, scan_scratch_size(1, pl->ntasks));
+    hip_check(launch_scan(st, 1, pl->ntasks, ns.p, sb.p, tot1.p, scr2.p), "step scan");
+    pl->nsteps = download(ctx, tot1.p, 1)[0];
+    if (pl->nsteps >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 product steps");
+    pl->steps = DBuf<uint64_t>(ctx, 2 * pl->nsteps);
+    pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
+    hip_check(launch_fill_steps(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p,
+                                pl->c_off.p, pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs,
+                                pl->steps.p, pl->sdesc.p),
+              "step fill");
+  }
   // temporaries go back to the allocator: later work on this stream is ordered after the fill
 }
 
@@ -195,6 +222,11 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   const bool generic = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
   P.desc = pl->desc.p;
   P.seg = pl->seg.p;
+  if (pl->step_path()) {  // one work item per tile, operands addressed by step records
+    P.desc = pl->sdesc.p;
+    P.seg = nullptr;
+    P.steps = pl->steps.p;
+  }
   std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
   if (pl->ctx->timing) {
@@ -640,12 +672,12 @@ bsm_status bsm_plan_cin_grad(bsm_plan pl, double beta, const double* dc_vals, do
 bsm_status bsm_tune_load(const char* path) {
   return guard([&] {
     int32_t v[kClasses];
+    std::string text;
     if (!path) {
       for (int c = 0; c < kClasses; ++c) v[c] = ((c / 4) % 2 == 1 && (c % 4) % 2 == 1) ? 1 : 0;
     } else {
       FILE* f = std::fopen(path, "rb");
       if (!f) fail(BSM_E_INVALID, "cannot open tuning file %s", path);
-      std::string text;
       char buf[4096];
       size_t got;
       while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
@@ -664,6 +696,40 @@ bsm_status bsm_tune_load(const char* path) {
       }
     }
     if (!set_variants(v)) fail(BSM_E_INVALID, "variants must be 0 or 1");
+    int32_t panel[2] = {32, 32};
+    if (path) {
+      const size_t pk = text.find("\"panel\"");
+      const size_t po = pk == std::string::npos ? pk : text.find('[', pk);
+      if (po != std::string::npos) {
+        const char* q = text.c_str() + po + 1;
+        for (int d = 0; d < 2; ++d) {
+          char* end = nullptr;
+          const long x = std::strtol(q, &end, 10);
+          if (end == q || x < 0 || x > (1 << 30)) fail(BSM_E_INVALID, "%s: \"panel\" needs 2 integers >= 0", path);
+          panel[d] = (int32_t)x;
+          q = end;
+          while (*q == ',' || *q == ' ') ++q;
+        }
+      }
+    }
+    g_panel[0] = panel[0];
+    g_panel[1] = panel[1];
+  });
+}
+
+bsm_status bsm_tune_panel(int32_t rows, int32_t cols) {
+  return guard([&] {
+    if (rows < 0 || cols < 0 || (rows == 0) != (cols == 0)) fail(BSM_E_INVALID, "panel sizes must be both 0 or both >= 1");
+    g_panel[0] = rows;
+    g_panel[1] = cols;
+  });
+}
+
+bsm_status bsm_tune_get_panel(int32_t* rows, int32_t* cols) {
+  return guard([&] {
+    if (!rows || !cols) fail(BSM_E_INVALID, "NULL output");
+    *rows = g_panel[0];
+    *cols = g_panel[1];
   });
 }
 

@@ -14,6 +14,7 @@ struct bsm_batch_s {
   bool generic = false;
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
   int32_t precision = BSM_PREC_FP64;
+  bool steps = false;  // the plans take the row-major step path
   DBuf<TaskDesc> desc;
   int32_t cls_tile[kClasses + 1] = {0};
   DBuf<ProbPtrs> ptab;
@@ -69,9 +70,13 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
   }
   set_device(ctx);
   hipStream_t st = ctx->stream;
-  // class boundaries of every plan's work items
+  // class boundaries of every plan's work items (step-path plans: one item per tile)
   std::vector<MergeRanges> rng(n);
-  {
+  b->steps = b->plans[0]->step_path();
+  if (b->steps) {
+    for (int32_t p = 0; p < n; ++p)
+      for (int c = 0; c <= kClasses; ++c) rng[p].sbeg[c] = b->plans[p]->cls_tile[c];
+  } else {
     DBuf<int64_t> bounds(ctx, (size_t)n * (kClasses + 1));
     for (int32_t p = 0; p < n; ++p) {
       bsm_plan pl = b->plans[p];
@@ -96,7 +101,8 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
   b->cls_tile[kClasses] = (int32_t)total;
   b->desc = DBuf<TaskDesc>(ctx, total);
   for (int32_t p = 0; p < n; ++p)
-    hip_check(launch_merge_desc(st, b->plans[p]->desc.p, rng[p], p, b->desc.p), "merge work items");
+    hip_check(launch_merge_desc(st, b->steps ? b->plans[p]->sdesc.p : b->plans[p]->desc.p, rng[p], p, b->desc.p),
+              "merge work items");
   b->ptab = DBuf<ProbPtrs>(ctx, n);
   hip_check(hipStreamSynchronize(st), "batch setup");
   return b.release();
@@ -126,6 +132,8 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
     t[p].beta = beta[p];
     t[p].inplace_skip = (out[p] == ci && beta[p] == 1.0) ? 1 : 0;
     t[p].pad = 0;
+    t[p].steps = b->steps ? pl->steps.p : nullptr;
+    t[p].pad2 = nullptr;
   }
   set_device(ctx);
   bool changed = b->hptab.size() != t.size();

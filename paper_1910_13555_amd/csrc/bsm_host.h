@@ -386,6 +386,14 @@ struct bsm_plan_s {
   int32_t cls_tile[kClasses + 1] = {0};  // class c's tiles: [cls_tile[c], cls_tile[c+1])
   DBuf<int64_t> seg;  // segment prefix per tile (ntasks + 1); seg[ntasks] = work items
   DBuf<TaskDesc> desc;
+  // row-major FP64 plans: step records (2 words each) and one work item per tile
+  DBuf<uint64_t> steps;
+  DBuf<TaskDesc> sdesc;
+  int64_t nsteps = 0;
+  bool step_path() const {
+    return opts.precision == BSM_PREC_FP64 && mx == bsm::kRowMajor && my == bsm::kRowMajor &&
+           mo == bsm::kRowMajor && !rowq.p;
+  }
   DBuf<int32_t> rowq;  // split factors for tensor layouts (optional)
   DBuf<double> na, nb; // stored-block norms of A and B (kept for the gradient when filtering)
   // gradient product lists, built on first use: [0] = dA, [1] = dB

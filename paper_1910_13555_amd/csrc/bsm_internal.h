@@ -58,7 +58,7 @@ enum SymField : int { kFBlk = 0, kFVals = 1, kFProd = 2, kFCand = 3, kFFlops = 4
 // One numeric work item: an output tile (at most kTile x kTile of one block)
 // and one segment of at most 64 of the block's products.  Segments of a tile
 // are consecutive; the first zeroes the accumulator, the last writes C.
-constexpr int32_t kTaskFirst = 1, kTaskLast = 2;
+constexpr int32_t kTaskFirst = 1, kTaskLast = 2, kTaskEmpty = 4;  // kTaskEmpty: a tile without products
 struct TaskDesc {
   int64_t pbeg;        // first product of the segment
   int64_t cout;        // offset of the output block
@@ -82,6 +82,8 @@ struct ProbPtrs {
   const int64_t* py;
   double alpha, beta;
   int32_t inplace_skip, pad;
+  const uint64_t* steps;  // step records (row-major path)
+  const void* pad2;
 };
 
 struct NumParams {
@@ -92,6 +94,7 @@ struct NumParams {
   double alpha = 1.0, beta = 0.0;
   const int64_t* px = nullptr;    // left offset | K << 48
   const int64_t* py = nullptr;    // right offset | q << 48
+  const uint64_t* steps = nullptr; // row-major path: step records (work items are tiles)
   const TaskDesc* desc = nullptr; // work items, tiles sorted by class
   const int64_t* seg = nullptr;   // device: first work item of each tile (ntiles + 1); null: one per tile
   const ProbPtrs* ptab = nullptr; // batches: per-problem buffers and scalars (replace the fields above)
@@ -140,6 +143,20 @@ int64_t scan_scratch_size(int nf, int64_t n);
 hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* base, int32_t* c_ptr,
                            int32_t* c_row, int32_t* c_col, int64_t* c_off, int64_t* cin_off_out,
                            int64_t* pptr, int64_t* px, int64_t* py, int2* tasks);
+// bsm_order.hip: reorder a class-sorted tile list into 2-D panels of the
+// output block grid (pr x pc blocks), keeping the class ranges.
+int64_t panel_order_scratch_bytes(int64_t ntiles);
+hipError_t launch_panel_order(hipStream_t s, int32_t ntiles, int2* tiles, const int32_t* c_row,
+                              const int32_t* c_col, const int32_t* rs, const int32_t* cs, int32_t pr,
+                              int32_t pc, void* scratch, int64_t scratch_bytes);
+// bsm_steps.hip: step lists of the row-major path (one work item per tile,
+// 16-byte step records; see the file's header).
+hipError_t launch_count_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* pptr,
+                              const int64_t* px, int64_t* nsteps);
+hipError_t launch_fill_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
+                             const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
+                             const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
+                             const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc);
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);

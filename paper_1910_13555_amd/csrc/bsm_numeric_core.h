@@ -66,6 +66,7 @@ constexpr int kKernels = kNumericKernels;
 constexpr int kKernVariant[kKernels] = {0, 0, 0, 1, 1};
 constexpr int kKernDepth[kKernels] = {2, 2, 2, 4, 2};
 constexpr int kKernWaves[kKernels] = {4, 3, 2, 4, 3};
+constexpr int kStepDepth[kKernels] = {2, 2, 2, 4, 2};   // pipeline depth of the row-major path
 
 // Kernel of class c under variant v: tiles up to 16 x 16, with 24, with 32
 // (variant 0); 16 x 16, larger (variant 1).
@@ -356,6 +357,238 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
   }
 }
 
+// Row-major path: the loop over this wavefront's tiles of one class, driven
+// by step records (bsm_steps.hip) -- every item is one tile, its steps are
+// records pbeg .. pbeg + np - 1.  Per step: two buffer resources from the
+// record (A: the block from A(r0, k0) on, reads guarded by the k test; B: the
+// block from B(k0, c0) on, sized so that rows past the step's valid k read
+// zero), one offset select per A operand, none for B (per-tile lane offsets),
+// and the matrix-core instructions.  A step's record is loaded with the
+// operands of the step D earlier, through the same in-order vector memory
+// counter, so its wait never holds back the pipeline; tile descriptors come
+// through scalar loads one tile ahead, and the fields the epilogue needs
+// travel with the step.
+template <int V, int NI, int NJ, bool CIN, bool BATCH, int D>
+__device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, int r, int stride) {
+  const int l = threadIdx.x;
+  const int lrA = V == 0 ? 4 * ((l >> 3) & 1) + (l & 3) : (l & 15);   // row inside an instruction tile
+  const int lcB = V == 0 ? 4 * ((l >> 2) & 1) + (l & 3) : (l & 15);   // column inside an instruction tile
+  const int lk = l >> 4;                                               // k inside an instruction k-step
+  constexpr int TI = V == 0 ? 8 : 16;
+  constexpr int NE = V == 0 ? 1 : 4;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+  int it = e0 + r;
+  if (it >= e1) return;
+
+  // ---- record cursor: walks the wavefront's steps D ahead of the issue
+  // cursor (tile pt, step ps of [ps, pe), descriptor of tile pt + stride
+  // one tile ahead)
+  TaskDesc pdn = desc_at(P, it);
+  int pt = it, ps = (int)pdn.pbeg, pe = ps + pdn.np;
+  const uint64_t* psteps = BATCH ? prob<BATCH>(P, pdn.pid).steps : P.steps;
+  const uint64_t* const first_rec = psteps + 2 * (int64_t)ps;   // a valid address for past-the-end loads
+  bool plive = true;
+  if (pt + stride < e1) pdn = desc_at(P, pt + stride);
+  auto load_rec = [&]() __attribute__((always_inline)) {
+    const uint64_t* q = plive ? psteps + 2 * (int64_t)ps : first_rec;
+    return *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(gptr(q));
+  };
+  auto padvance = [&]() __attribute__((always_inline)) {
+    if (!plive) return;
+    if (++ps < pe) return;
+    pt += stride;
+    if (pt >= e1) {
+      plive = false;
+      return;
+    }
+    if (BATCH) psteps = prob<BATCH>(P, pdn.pid).steps;
+    ps = (int)pdn.pbeg;
+    pe = ps + pdn.np;
+    if (pt + stride < e1) pdn = desc_at(P, pt + stride);
+  };
+
+  // ---- issue cursor: tile it (descriptor id), step s of [s, se)
+  TaskDesc id = desc_at(P, it);
+  TaskDesc nd = id;                        // descriptor of tile it + stride
+  if (it + stride < e1) nd = desc_at(P, it + stride);
+  int s = (int)id.pbeg, se = s + id.np;
+  const double* X = nullptr;
+  const double* Y = nullptr;
+  int mt = 0, N8 = 0, c08 = 0;
+  uint32_t offB[NJ][4];
+  int rowA[NI];
+  auto enter = [&](const TaskDesc& d) __attribute__((always_inline)) {
+    const OpPtrs o = op_ptrs<BATCH>(P, d.pid);
+    X = o.X;
+    Y = o.Y;
+    const int r0 = d.tr * kTile, c0 = d.tc * kTile;
+    mt = min(kTile, (int)d.M - r0);
+    const int nt = min(kTile, (int)d.N - c0);
+    N8 = (int)d.N * 8;
+    c08 = c0 * 8;
+#pragma unroll
+    for (int y = 0; y < NJ; ++y) {
+      const int c = TI * y + lcB;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        offB[y][ks] = c < nt ? (uint32_t)((4 * ks + lk) * (int)d.N + c) * 8u : kOob;
+    }
+#pragma unroll
+    for (int x = 0; x < NI; ++x) {
+      const int rr = TI * x + lrA;
+      rowA[x] = rr < mt ? rr : -1;
+    }
+  };
+  enter(id);
+
+  constexpr bool PRE = CIN;
+  double A[D][NI][4], B[D][NJ][4];
+  double Cb[D][PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1];
+  u32x4 R[D];                              // record of the step issued next into this buffer
+  // per buffer: flags (1 live, 2 tile's last step, 4 k-steps 2-3 needed) and
+  // the epilogue's fields of the tile
+  int tflag[D], tpid[D], tmn[D], ttile[D];
+  int64_t tcout[D];
+
+  auto issue = [&](double (&a)[NI][4], double (&b)[NJ][4], double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1],
+                   u32x4& rec, int& flag, int& pid, int& mn, int& tile, int64_t& cout) __attribute__((always_inline)) {
+    const bool live = it < e1;
+    const uint64_t w0 = ((uint64_t)__builtin_amdgcn_readfirstlane(rec[1]) << 32) | __builtin_amdgcn_readfirstlane(rec[0]);
+    const uint64_t w1 = ((uint64_t)__builtin_amdgcn_readfirstlane(rec[3]) << 32) | __builtin_amdgcn_readfirstlane(rec[2]);
+    // the record for this buffer's next step, D steps ahead
+    rec = load_rec();
+    padvance();
+    const int K8 = (int)(w0 >> 48) * 8;
+    const int kv = live ? (int)(w1 >> 48) : 0;
+    const auto ra = make_rsrc((const double*)((const char*)X + (w0 & kMask48)), 0x7ffffff8u);
+    const auto rb = make_rsrc((const double*)((const char*)Y + (w1 & kMask48)),
+                              kv > 0 ? (uint32_t)(kv * N8 - c08) : 0u);
+#pragma unroll
+    for (int x = 0; x < NI; ++x) {
+      const uint32_t base = rowA[x] >= 0 ? (uint32_t)(rowA[x] * K8 + lk * 8) : kOob;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) a[x][ks] = buf_load(ra, 4 * ks + lk < kv ? base + 32u * ks : kOob);
+    }
+#pragma unroll
+    for (int y = 0; y < NJ; ++y)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) b[y][ks] = buf_load(rb, offB[y][ks]);
+    const bool last = s + 1 >= se;
+    if constexpr (PRE) {
+      // the tile's C_in, requested with its last step (every step issues
+      // these loads, out of range unless they are needed)
+      const ProbPtrs pp = prob<BATCH>(P, id.pid);
+      const bool want = live && last && pp.beta != 0.0 && id.cin >= 0;
+      const auto rc = make_rsrc(want ? pp.cin + id.cin : nullptr, want ? (uint32_t)(id.M * id.N) * 8u : 0u);
+      const int r0 = id.tr * kTile, c0 = id.tc * kTile;
+      const int nt = min(kTile, (int)id.N - c0);
+#pragma unroll
+      for (int x = 0; x < NI; ++x)
+#pragma unroll
+        for (int y = 0; y < NJ; ++y)
+#pragma unroll
+          for (int e = 0; e < NE; ++e) {
+            const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+            const int cc = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+            const uint32_t off = (rr < mt && cc < nt) ? (uint32_t)((r0 + rr) * id.N + c0 + cc) * 8u : kOob;
+            cb[x][y][e] = buf_load(rc, off);
+          }
+    }
+    flag = live ? (1 | (last ? 2 : 0) | (kv > 8 ? 4 : 0)) : 0;
+    pid = id.pid;
+    mn = (int)id.M | ((int)id.N << 16);
+    tile = (int)id.tr | ((int)id.tc << 16) | ((id.flags & kTaskEmpty) ? (1 << 31) : 0);
+    cout = id.cout;
+    if (!live) return;
+    if (++s < se) return;
+    it += stride;
+    if (it >= e1) return;
+    id = nd;
+    s = (int)id.pbeg;
+    se = s + id.np;
+    enter(id);
+    if (it + stride < e1) nd = desc_at(P, it + stride);
+  };
+
+  using Acc = typename std::conditional<V == 0, double, f64x4>::type;
+  Acc acc[NI][NJ];
+#pragma unroll
+  for (int x = 0; x < NI; ++x)
+#pragma unroll
+    for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
+  auto epilogue = [&](const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1], int pid, int mn, int tile,
+                      int64_t cout) __attribute__((always_inline)) {
+    const int M = mn & 0xffff, N = mn >> 16;
+    const int er0 = (tile & 0xffff) * kTile, ec0 = ((tile >> 16) & 0x7fff) * kTile;
+    const int emt = min(kTile, M - er0), ent = min(kTile, N - ec0);
+    const ProbPtrs pp = prob<BATCH>(P, pid);
+    // a tile without products is left untouched when C is updated in place
+    // with beta = 1
+    if (!(pp.inplace_skip && tile < 0)) {
+      const auto ro = make_rsrc(pp.out + cout, (uint32_t)(M * N) * 8u);
+      const bool use_cin = PRE && pp.beta != 0.0;
+#pragma unroll
+      for (int x = 0; x < NI; ++x)
+#pragma unroll
+        for (int y = 0; y < NJ; ++y)
+#pragma unroll
+          for (int e = 0; e < NE; ++e) {
+            const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+            const int cc = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+            double av;
+            if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
+            // branch-free: lanes outside the tile get an offset past the block
+            const uint32_t in = (uint32_t)((rr - emt) & (cc - ent)) >> 31;   // rr < emt && cc < ent
+            const uint32_t off = ((uint32_t)((er0 + rr) * N + ec0 + cc) * 8u) | ((in ^ 1u) << 31);
+            double v = pp.alpha * av;
+            if constexpr (PRE) {
+              if (use_cin) v += pp.beta * cb[x][y][e];   // zero where the tile has no C_in block
+            }
+            buf_store(ro, off, v);
+          }
+    }
+#pragma unroll
+    for (int x = 0; x < NI; ++x)
+#pragma unroll
+      for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
+  };
+  auto compute = [&](const double (&a)[NI][4], const double (&b)[NJ][4], bool deep) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (ks < 2 || deep) {
+#pragma unroll
+        for (int x = 0; x < NI; ++x)
+#pragma unroll
+          for (int y = 0; y < NJ; ++y) {
+            if constexpr (V == 0)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+            else
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+          }
+      }
+    }
+  };
+
+  // prologue: the records of the first D steps, then their operands
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    R[d] = load_rec();
+    padvance();
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d]);
+  while (true) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (!(tflag[d] & 1)) return;
+      compute(A[d], B[d], (tflag[d] & 4) != 0);
+      if (tflag[d] & 2) epilogue(Cb[d], tpid[d], tmn[d], ttile[d], tcout[d]);
+      issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d]);
+    }
+  }
+}
+
 // Persistent kernel KID.  Wavefronts [W.w[c], W.w[c+1]) serve class c (a
 // multiple of 8 of them).  Workgroups are dealt to the 8 XCDs round-robin, so
 // local wavefront w runs on XCD w % 8; each XCD owns one contiguous eighth of
@@ -376,7 +609,7 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
   const int e0 = slice_start(P.desc, d0, d1, x, kXcd), e1 = slice_start(P.desc, d0, d1, x + 1, kXcd);
   if (e0 + r >= e1) return;
   constexpr int V = kKernVariant[KID];
-  constexpr int DP = kKernDepth[KID];
+  constexpr int DP = GEN ? kKernDepth[KID] : kStepDepth[KID];
   // one call per distinct instruction grid of this kernel's classes
   const int ni = V == 0 ? c / 4 + 1 : (c / 4 + 2) / 2;
   const int nj = V == 0 ? c % 4 + 1 : (c % 4 + 2) / 2;
@@ -385,7 +618,8 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
   case NI_ * 8 + NJ_:                                                                    \
     if constexpr (V == 0 ? kernel_of((NI_ - 1) * 4 + NJ_ - 1, 0) == KID                  \
                          : kernel_of((2 * NI_ - 1) * 4 + 2 * NJ_ - 1, 1) == KID)         \
-      run_tiles<V, NI_, NJ_, GEN, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd);                \
+      if constexpr (GEN) run_tiles<V, NI_, NJ_, GEN, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd); \
+      else run_steps<V, NI_, NJ_, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd);                 \
     break;
     BSM_SHAPE(1, 1) BSM_SHAPE(1, 2) BSM_SHAPE(1, 3) BSM_SHAPE(1, 4)
     BSM_SHAPE(2, 1) BSM_SHAPE(2, 2) BSM_SHAPE(2, 3) BSM_SHAPE(2, 4)

@@ -1,7 +1,8 @@
 """Autotuner of the numeric phase: picks, per output tile class, the
-matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4) that runs a workload
-fastest, by timing the numeric phase on the GPU (coordinate descent over the
-16 classes, starting from the built-in table), and writes the table as JSON
+matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4), then the output
+panel of the work order, that run a workload fastest, by timing the numeric
+phase on the GPU (coordinate descent over the 16 classes starting from the
+built-in table, then a scan of panel edges), and writes the result as JSON
 for bsm_tune_load.
 
 Usage: python -m paper_1910_13555_amd.tune [--workload banded|batched|tall_skinny]
@@ -79,9 +80,20 @@ def tune(workload="banded", reps=10, min_gain=0.02):
         if t < best * (1.0 - min_gain):
             table, best = trial, t
     bsm.bsm_tune_set(table)
-    del keep
-    return {"workload": workload, "variant": table, "default_ms": start, "tuned_ms": best,
-            "trials": trials}
+    del keep, fn
+    # work order: output panel edge (plans are rebuilt, the order is fixed at plan time)
+    panel = bsm.bsm_tune_get_panel()
+    for edge in (0, 16, 64, 128):
+        bsm.bsm_tune_panel(edge, edge)
+        fn, keep = _runner(workload)
+        t = _time(fn, reps)
+        trials.append({"panel": edge, "ms": t})
+        del keep, fn
+        if t < best * (1.0 - min_gain):
+            panel, best = (edge, edge), t
+    bsm.bsm_tune_panel(*panel)
+    return {"workload": workload, "variant": table, "panel": list(panel), "default_ms": start,
+            "tuned_ms": best, "trials": trials}
 
 
 def main():
@@ -96,7 +108,7 @@ def main():
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
-    print(json.dumps({k: res[k] for k in ("workload", "variant", "default_ms", "tuned_ms")}), flush=True)
+    print(json.dumps({k: res[k] for k in ("workload", "variant", "panel", "default_ms", "tuned_ms")}), flush=True)
 
 
 if __name__ == "__main__":

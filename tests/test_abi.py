@@ -133,6 +133,14 @@ def test_tuning_table_roundtrip(tmp_path):
             bsm.bsm_tune_load(bad)
         with pytest.raises(bsm.BsmError):
             bsm.bsm_tune_load(tmp_path / "missing.json")
+        bsm.bsm_tune_panel(0, 0)
+        assert bsm.bsm_tune_get_panel() == (0, 0)
+        with pytest.raises(bsm.BsmError):
+            bsm.bsm_tune_panel(0, 8)
+        f.write_text('{"variant": [0, 1, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 1, 1, 1, 1], "panel": [64, 16]}')
+        bsm.bsm_tune_load(f)
+        assert bsm.bsm_tune_get_panel() == (64, 16)
     finally:
         bsm.bsm_tune_load(None)
     assert bsm.bsm_tune_get() == default
+    assert bsm.bsm_tune_get_panel() == (32, 32)

@@ -188,3 +188,22 @@ def test_random_cases_forced_variant(bsm, variants, variant, seed):
     if tb:
         dB = workloads.random_matrix(rng, dB["col_sizes"], dB["row_sizes"], 0.5)
     check_against_oracle(bsm, dA, dB, dC, 1.5, 0.5 if dC is not None else 0.0, 0.0, ta, tb)
+
+
+def test_work_order_panels_bit_identical(bsm):
+    """The panel order of the work items changes only which wavefront runs a
+    tile: results are bit-identical for every panel shape."""
+    d = workloads.banded(nblk=150, seed_tag=31)
+    A = bsm.BlockSparseMatrix.from_workload(d["A"])
+    B = bsm.BlockSparseMatrix.from_workload(d["B"])
+    outs = []
+    try:
+        for pr, pc in ((0, 0), (32, 32), (3, 5), (1, 1), (200, 7)):
+            bsm.bsm_tune_panel(pr, pc)
+            outs.append(bsm.matmul(A, B, filter_eps=d["eps"]).values.clone())
+            torch.cuda.synchronize()
+    finally:
+        bsm.bsm_tune_load(None)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    check_against_oracle(bsm, d["A"], d["B"], eps=d["eps"])
