@@ -253,6 +253,74 @@ def batched_section(bsm, reps, stream):
     return res
 
 
+def tall_skinny_section(bsm, reps, stream):
+    """The tall-skinny case (Sec. 3.1 shape): full multiply (plan + numeric) and
+    the numeric phase alone, C_in dense with beta = 1 accumulated in place."""
+    import torch
+    import workloads
+    d = workloads.tall_skinny()
+    ctx = bsm.default_context()
+    A = bsm.BlockSparseMatrix.from_workload(d["A"], ctx=ctx)
+    B = bsm.BlockSparseMatrix.from_workload(d["B"], ctx=ctx)
+    Cm = bsm.BlockSparseMatrix.from_workload(d["C"], ctx=ctx)
+    cin = Cm.values.clone()
+
+    def full():
+        plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, Cm.pattern, d["eps"])
+        plan.execute(d["alpha"], A.values, B.values, d["beta"], cin, cin)
+        return plan
+
+    plan = full()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = [full() for _ in range(reps)]
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - t0) * 1e3 / reps
+    del plans
+    ms = time_events(lambda: plan.execute(d["alpha"], A.values, B.values, d["beta"], cin, cin), reps, stream)
+    F = plan.info["flops"]
+    return {"workload": d["name"], "products": plan.info["nprod"], "useful_gflop": F / 1e9,
+            "ms_per_multiply": full_ms, "gflops": F / (full_ms * 1e-3) / 1e9,
+            "numeric_ms": ms, "numeric_gflops": F / (ms * 1e-3) / 1e9}
+
+
+def rank3_section(bsm, reps, stream):
+    """The rank-3 contraction T[mu,nu,P] M[nu,lambda] -> R[mu,lambda,P] (Sec. 4):
+    forward (plan + numeric) and the autograd backward."""
+    import numpy as np
+    import torch
+    import workloads
+    d = workloads.rank3()
+    ctx = bsm.default_context()
+    sz = d["sizes"]
+    T = bsm.BlockSparseTensor.from_lists([sz["mu"], sz["nu"], sz["P"]], d["T_idx"], d["T_values"], ctx=ctx)
+    Mi = np.stack([d["M_rows"], d["M_cols"]], 1).astype(np.int32)
+    M = bsm.BlockSparseTensor.from_lists([sz["nu"], sz["lam"]], Mi, d["M_values"], ctx=ctx)
+    T.values.requires_grad_(True)
+    M.values.requires_grad_(True)
+    out = bsm.contract("mnP,nl->mlP", T, M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = bsm.contract("mnP,nl->mlP", T, M)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / reps
+    F = out.plan.info["flops"]
+    g = torch.ones_like(out.values)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        T.values.grad = None
+        M.values.grad = None
+        out = bsm.contract("mnP,nl->mlP", T, M)
+        out.values.backward(g)
+    torch.cuda.synchronize()
+    fb_ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"workload": d["name"], "products": out.plan.info["nprod"], "useful_gflop_forward": F / 1e9,
+            "forward_ms": fwd_ms, "forward_gflops": F / (fwd_ms * 1e-3) / 1e9,
+            "forward_backward_ms": fb_ms, "forward_backward_gflops": 3 * F / (fb_ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +329,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the split-precision and batched sections")
+    ap.add_argument("--rank3", action="store_true",
+                    help="also run the rank-3 contraction (13.5 GB tensor; about a minute of setup)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device-to-device copy of this many bytes "
                          "(calibrates HBM byte counters of a profiler run)")
@@ -309,22 +379,21 @@ def main():
         return plan, out
 
     for _ in range(args.warmup):
-        step()
+        plan, out = step()
+        plan = None
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     t0 = time.perf_counter()
-    plans = []
+    plan = None
     for k in range(args.steps):
+        plan = None     # the previous step's plan returns its memory to the library's cache
         plan, out = step(evs[k])
-        plans.append(plan)  # keep alive until the clock stops (destroy is host work)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     numeric_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
-    plan = plans[-1]
     info = plan.info
-    del plans
 
     # numeric phase alone (plan reuse, as in repeated multiplies with a fixed pattern)
     reuse_ms = time_events(lambda: plan.execute(1.0, A.values, B.values, 0.0, None, out), args.steps,
@@ -363,6 +432,9 @@ def main():
         del plan, out
         torch.cuda.empty_cache()
         res["batched"] = batched_section(bsm, max(2, args.steps // 4), stream)
+        res["tall_skinny"] = tall_skinny_section(bsm, max(2, args.steps // 4), stream)
+    if args.rank3:
+        res["rank3"] = rank3_section(bsm, 3, stream)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(res), flush=True)

@@ -276,7 +276,7 @@ bsm_status bsm_plan_t3_pattern(bsm_plan plan, bsm_tpattern* out);
  * class and writes a JSON file {"variant": [16 integers], ...}.
  * bsm_tune_load(path) reads such a file (BSM_E_INVALID if unreadable or
  * malformed); path NULL restores the built-in defaults (16x16x4 where both
- * padded edges are multiples of 16; 32 x 32 panels). */
+ * padded edges are multiples of 16; canonical work order). */
 bsm_status bsm_tune_load(const char* path);
 /* Work order of the numeric phase: output tiles of a class are visited in
  * panels of rows x cols output blocks (panels row by row, canonical order

@@ -18,7 +18,7 @@ namespace bsm_host {
 extern const bsm_mm_opts kDefaultOpts;
 const bsm_mm_opts kDefaultOpts = {0, 0, 0, BSM_PREC_FP64};
 // Output panel (block rows x block columns) of the numeric work order; 0: canonical order.
-int32_t g_panel[2] = {32, 32};
+int32_t g_panel[2] = {0, 0};
 
 // Work items of the numeric kernel from a tile list: one per (tile, segment
 // of <= 64 products), written on the device; `seg` ends with their count.
@@ -155,23 +155,34 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                                  pl->c_cs, pr, pc, sc.p, sb),
               "panel order");
   }
-  build_desc(ctx, pl->ntasks, pl->tasks.p, pl->c_row.p, pl->c_col.p, pl->c_off.p, pl->cin_off.p,
-             pl->pptr.p, pl->c_rs, pl->c_cs, pl->rowq.p, pl->nprod,
-             max_tiles(ta ? A->h_cs : A->h_rs, tb ? B->h_rs : B->h_cs), pl->seg, pl->desc);
-  if (pl->step_path() && pl->ntasks > 0) {
-    // step records: per-tile counts, scan, fill (the total is read back once)
-    DBuf<int64_t> ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1), tot1(ctx, 1);
-    hip_check(launch_count_steps(st, (int32_t)pl->ntasks, pl->tasks.p, pl->pptr.p, pl->px.p, ns.p), "step count");
-    DBuf<int64_t> scr2(ctx, scan_scratch_size(1, pl->ntasks));
-    hip_check(launch_scan(st, 1, pl->ntasks, ns.p, sb.p, tot1.p, scr2.p), "step scan");
-    pl->nsteps = download(ctx, tot1.p, 1)[0];
+  if (!pl->step_path()) {
+    build_desc(ctx, pl->ntasks, pl->tasks.p, pl->c_row.p, pl->c_col.p, pl->c_off.p, pl->cin_off.p,
+               pl->pptr.p, pl->c_rs, pl->c_cs, pl->rowq.p, pl->nprod,
+               max_tiles(ta ? A->h_cs : A->h_rs, tb ? B->h_rs : B->h_cs), pl->seg, pl->desc);
+  } else if (pl->ntasks > 0) {
+    // step records (no readback: the symbolic count bounds them, tiles
+    // without products add one step each)
+    pl->nsteps = h[kFSteps] + pl->ntasks;
     if (pl->nsteps >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 product steps");
+    DBuf<int64_t> ch(ctx, pl->nprod + 1), chs(ctx, pl->nprod + 2), ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1);
+    DBuf<int32_t> b2t(ctx, pl->c_nblk);
+    hip_check(launch_product_chunks(st, pl->nprod, pl->px.p, ch.p), "product chunks");
+    DBuf<int64_t> scr1(ctx, scan_scratch_size(1, std::max<int64_t>(pl->nprod, 1)));
+    hip_check(launch_scan(st, 1, pl->nprod, ch.p, chs.p, nullptr, scr1.p), "chunk scan");
+    hip_check(launch_tile_steps(st, (int32_t)pl->ntasks, pl->c_nblk, pl->tasks.p, pl->pptr.p, chs.p, pl->c_row.p,
+                                pl->c_col.p, pl->c_rs, pl->c_cs, ns.p, b2t.p),
+              "tile steps");
+    DBuf<int64_t> scr2(ctx, scan_scratch_size(1, pl->ntasks));
+    hip_check(launch_scan(st, 1, pl->ntasks, ns.p, sb.p, nullptr, scr2.p), "step scan");
     pl->steps = DBuf<uint64_t>(ctx, 2 * pl->nsteps);
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
-    hip_check(launch_fill_steps(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p,
-                                pl->c_off.p, pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs,
-                                pl->steps.p, pl->sdesc.p),
-              "step fill");
+    hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
+                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, pl->steps.p,
+                                pl->sdesc.p),
+              "work items");
+    hip_check(launch_product_steps(st, pl->nprod, pl->c_nblk, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
+                                   pl->c_cs, pl->px.p, pl->py.p, pl->steps.p),
+              "product steps");
   }
   // temporaries go back to the allocator: later work on this stream is ordered after the fill
 }
@@ -696,7 +707,7 @@ bsm_status bsm_tune_load(const char* path) {
       }
     }
     if (!set_variants(v)) fail(BSM_E_INVALID, "variants must be 0 or 1");
-    int32_t panel[2] = {32, 32};
+    int32_t panel[2] = {0, 0};
     if (path) {
       const size_t pk = text.find("\"panel\"");
       const size_t po = pk == std::string::npos ? pk : text.find('[', pk);

@@ -133,9 +133,13 @@ struct bsm_ctx_s {
   bool timing = false;
   hipEvent_t ev[2 * bsm::kNumericKernels] = {};
   int32_t launched[bsm::kNumericKernels] = {};
+  // pinned host staging for small readbacks
+  static constexpr size_t kStaging = 4096;
+  void* staging = nullptr;
   ~bsm_ctx_s() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (staging) (void)hipHostFree(staging);
   }
 };
 
@@ -216,8 +220,16 @@ template <class T>
 std::vector<T> download(bsm_ctx c, const T* d, size_t n) {
   std::vector<T> h(n);
   if (n) {
-    hip_check(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, c->stream), "download");
-    hip_check(hipStreamSynchronize(c->stream), "download sync");
+    const size_t bytes = sizeof(T) * n;
+    if (bytes <= bsm_ctx_s::kStaging) {  // small readbacks go through pinned staging memory
+      if (!c->staging) hip_check(hipHostMalloc(&c->staging, bsm_ctx_s::kStaging, hipHostMallocDefault), "pinned staging");
+      hip_check(hipMemcpyAsync(c->staging, d, bytes, hipMemcpyDeviceToHost, c->stream), "download");
+      hip_check(hipStreamSynchronize(c->stream), "download sync");
+      std::memcpy(h.data(), c->staging, bytes);
+    } else {
+      hip_check(hipMemcpyAsync(h.data(), d, bytes, hipMemcpyDeviceToHost, c->stream), "download");
+      hip_check(hipStreamSynchronize(c->stream), "download sync");
+    }
   }
   return h;
 }

@@ -15,7 +15,7 @@ constexpr int kSymChunk = 2048;               // output columns per bitmap pass
 constexpr int kSymWords = kSymChunk / 32;     // = one 32-bit word per lane of a wavefront
 constexpr int kTile = 32;                     // max output tile edge per work item
 constexpr int kClasses = 16;                  // tile classes: padded rows x columns in {8,16,24,32}^2
-constexpr int kSymFields = 6 + kClasses;      // per-row counts of the symbolic phase
+constexpr int kSymFields = 7 + kClasses;      // per-row counts of the symbolic phase
 
 // Tile class of an mt x nt tile (1..32 each): (ceil(mt/8)-1)*4 + ceil(nt/8)-1.
 __host__ __device__ inline int tile_class(int mt, int nt) { return ((mt + 7) / 8 - 1) * 4 + ((nt + 7) / 8 - 1); }
@@ -52,8 +52,12 @@ struct SymParams {
 };
 
 // Symbolic count fields (k_sym_count, then prefix sums); field kFClass + c
-// counts the tiles of class c.
-enum SymField : int { kFBlk = 0, kFVals = 1, kFProd = 2, kFCand = 3, kFFlops = 4, kFTiles = 5, kFClass = 6 };
+// counts the tiles of class c; kFSteps counts the 16-k steps of the kept
+// products over all tiles of their output blocks.
+enum SymField : int {
+  kFBlk = 0, kFVals = 1, kFProd = 2, kFCand = 3, kFFlops = 4, kFTiles = 5, kFClass = 6,
+  kFSteps = 6 + kClasses
+};
 
 // One numeric work item: an output tile (at most kTile x kTile of one block)
 // and one segment of at most 64 of the block's products.  Segments of a tile
@@ -157,6 +161,21 @@ hipError_t launch_fill_steps(hipStream_t s, int32_t ntiles, const int2* tiles, c
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
                              const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc);
+// Product-parallel step building: chunks per product; per-tile step counts
+// (and the single-tile block map); work items, empty-tile steps and steps of
+// multi-tile blocks; steps of single-tile blocks per product.
+hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, int64_t* chunks);
+hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
+                             const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
+                             const int32_t* cs, int64_t* nsteps, int32_t* blk2tile);
+hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
+                             const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
+                             const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
+                             const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc);
+hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
+                                const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
+                                const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
+                                uint64_t* steps);
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);

@@ -77,7 +77,156 @@ __global__ void k_fill_steps(int32_t ntiles, const int2* __restrict__ tiles, con
   }
 }
 
+// Product-parallel form.  chunks[p] = ceil(K_p / 16) for every product.
+__global__ void k_product_chunks(int64_t nprod, const int64_t* __restrict__ px, int64_t* __restrict__ chunks) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprod) return;
+  const int K = (int)((uint64_t)px[p] >> 48);
+  chunks[p] = (K + kStepK - 1) / kStepK;
+}
+
+// Per tile: step count from the product chunk prefix (chs, exclusive, nprod + 1
+// entries); blk2tile[t] = w for blocks that are a single tile, -1 otherwise.
+__global__ void k_tile_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ pptr,
+                             const int64_t* __restrict__ chs, const int32_t* __restrict__ c_row,
+                             const int32_t* __restrict__ c_col, const int32_t* __restrict__ rs,
+                             const int32_t* __restrict__ cs, int64_t* __restrict__ nsteps,
+                             int32_t* __restrict__ blk2tile) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= ntiles) return;
+  const int t = tiles[w].x;
+  const int64_t n = chs[pptr[t + 1]] - chs[pptr[t]];
+  nsteps[w] = n > 0 ? n : 1;
+  const bool single = rs[c_row[t]] <= kTile && cs[c_col[t]] <= kTile;
+  if (single) blk2tile[t] = w;
+}
+
+// Per tile: the work item; the one step of a tile without products; the
+// steps of tiles of multi-tile blocks (serially, those are rare).
+__global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ sbase,
+                             const int32_t* __restrict__ c_row, const int32_t* __restrict__ c_col,
+                             const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
+                             const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
+                             const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
+                             const int32_t* __restrict__ cs, uint64_t* __restrict__ steps,
+                             TaskDesc* __restrict__ desc) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= ntiles) return;
+  const int t = tiles[w].x;
+  const int tr = tiles[w].y & 0xffff, tc = tiles[w].y >> 16;
+  const int i = c_row[t], j = c_col[t];
+  const int M = rs[i], N = cs[j];
+  const int r0 = tr * kTile, c0 = tc * kTile;
+  const int mt = min(kTile, M - r0), nt = min(kTile, N - c0);
+  const int64_t p0 = pptr[t], p1 = pptr[t + 1];
+  int64_t s = sbase[w];
+  TaskDesc d;
+  d.pbeg = s;
+  d.cout = c_off[t];
+  d.cin = cin_off ? cin_off[t] : -1;
+  d.np = (int32_t)(sbase[w + 1] - s);
+  d.flags = kTaskFirst | kTaskLast | (p0 == p1 ? kTaskEmpty : 0);
+  d.M = (uint16_t)M;
+  d.N = (uint16_t)N;
+  d.tr = (uint16_t)tr;
+  d.tc = (uint16_t)tc;
+  d.qo = 1;
+  d.cls = (uint16_t)tile_class(mt, nt);
+  d.pid = 0;
+  desc[w] = d;
+  if (p0 == p1) {
+    steps[2 * s] = 0;
+    steps[2 * s + 1] = 0;
+    return;
+  }
+  if (M <= kTile && N <= kTile) return;  // written per product
+  for (int64_t p = p0; p < p1; ++p) {
+    const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
+    const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
+    const int K = (int)(xw >> 48);
+    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) {
+      const uint64_t kv = (uint64_t)min(kStepK, K - k0);
+      steps[2 * s] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
+      steps[2 * s + 1] = ((uint64_t)(yo + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
+    }
+  }
+}
+
+// Per product of a single-tile block: its steps at the tile's base plus the
+// chunks of the block's earlier products.
+__global__ void k_product_steps(int64_t nprod, int64_t nblk, const int64_t* __restrict__ pptr,
+                                const int64_t* __restrict__ chs, const int32_t* __restrict__ blk2tile,
+                                const int64_t* __restrict__ sbase, const int32_t* __restrict__ c_col,
+                                const int32_t* __restrict__ cs, const int64_t* __restrict__ px,
+                                const int64_t* __restrict__ py, uint64_t* __restrict__ steps) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprod) return;
+  int64_t lo = 0, hi = nblk - 1;      // the block t with pptr[t] <= p < pptr[t + 1]
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (pptr[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const int64_t t = lo;
+  const int w = blk2tile[t];
+  if (w < 0) return;
+  const int N = cs[c_col[t]];
+  int64_t s = sbase[w] + (chs[p] - chs[pptr[t]]);
+  const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
+  const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
+  const int K = (int)(xw >> 48);
+  for (int k0 = 0; k0 < K; k0 += kStepK, ++s) {
+    const uint64_t kv = (uint64_t)min(kStepK, K - k0);
+    steps[2 * s] = ((uint64_t)(xo + k0) * 8u) | ((uint64_t)K << 48);
+    steps[2 * s + 1] = ((uint64_t)(yo + (int64_t)k0 * N) * 8u) | (kv << 48);
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, int64_t* chunks) {
+  if (nprod == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_product_chunks, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, px, chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
+                             const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
+                             const int32_t* cs, int64_t* nsteps, int32_t* blk2tile) {
+  if (nblk > 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, blk2tile, nblk, -1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, pptr, chs, c_row,
+                     c_col, rs, cs, nsteps, blk2tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
+                             const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
+                             const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
+                             const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
+                     c_col, c_off, cin_off, pptr, px, py, rs, cs, steps, desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
+                                const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
+                                const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
+                                uint64_t* steps) {
+  if (nprod == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, nblk, pptr,
+                     chs, blk2tile, sbase, c_col, cs, px, py, steps);
+  return hipGetLastError();
+}
 
 hipError_t launch_count_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* pptr,
                               const int64_t* px, int64_t* nsteps) {

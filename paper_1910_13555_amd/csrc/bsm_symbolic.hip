@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
   const int nr = P.a.nr, nc = P.b.nc;
   const int tid = threadIdx.x;
   const int m = P.rs[row];
-  int64_t nblk = 0, nvals = 0, nprod = 0, ncand = 0, flops = 0, ntiles = 0;
+  int64_t nblk = 0, nvals = 0, nprod = 0, ncand = 0, flops = 0, ntiles = 0, nsteps = 0;
   if (tid < kClasses) S.cls[tid] = 0;
   for (int jlo = 0; jlo < nc; jlo += kSymChunk) {
     const int jhi = min(nc, jlo + kSymChunk);
@@ -231,6 +231,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
       if (!c.keep || (P.retain && !bit_test(S.cm, c.j - jlo))) return;
       ++nprod;
       flops += 2 * (int64_t)m * P.ks[c.k] * P.cs[c.j];
+      nsteps += (int64_t)((P.ks[c.k] + 15) / 16) * num_tiles(m, P.cs[c.j]);
       bit_set(S.bm, c.j - jlo);
     });
     if (tid < kSymWords && tid * 32 < jhi - jlo) {
@@ -250,6 +251,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
   ncand = block_sum_i64(ncand, S.red);
   flops = block_sum_i64(flops, S.red);
   ntiles = block_sum_i64(ntiles, S.red);
+  nsteps = block_sum_i64(nsteps, S.red);
   if (tid == 0) {
     cnt[0 * (int64_t)nr + row] = nblk;
     cnt[1 * (int64_t)nr + row] = nvals;
@@ -259,6 +261,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
     cnt[5 * (int64_t)nr + row] = ntiles;
   }
   if (tid < kClasses) cnt[(int64_t)(kFClass + tid) * nr + row] = S.cls[tid];
+  if (tid == 0) cnt[(int64_t)kFSteps * nr + row] = nsteps;
 }
 
 hipError_t launch_sym_count(hipStream_t s, const SymParams& p, int64_t* cnt) {

@@ -83,7 +83,7 @@ def tune(workload="banded", reps=10, min_gain=0.02):
     del keep, fn
     # work order: output panel edge (plans are rebuilt, the order is fixed at plan time)
     panel = bsm.bsm_tune_get_panel()
-    for edge in (0, 16, 64, 128):
+    for edge in (16, 32, 64):
         bsm.bsm_tune_panel(edge, edge)
         fn, keep = _runner(workload)
         t = _time(fn, reps)

@@ -143,4 +143,4 @@ def test_tuning_table_roundtrip(tmp_path):
     finally:
         bsm.bsm_tune_load(None)
     assert bsm.bsm_tune_get() == default
-    assert bsm.bsm_tune_get_panel() == (32, 32)
+    assert bsm.bsm_tune_get_panel() == (0, 0)
