@@ -217,6 +217,9 @@ def batched_section(bsm, reps, stream):
     import workloads
     probs = workloads.batched()
     ctx = bsm.default_context()
+    tuned = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "batched.json")
+    if os.path.exists(tuned):
+        bsm.bsm_tune_load(tuned)          # the autotuner's table for this workload
     mats = [(bsm.BlockSparseMatrix.from_workload(p["A"], ctx=ctx),
              bsm.BlockSparseMatrix.from_workload(p["B"], ctx=ctx)) for p in probs]
     a = [m[0].values for m in mats]
@@ -250,6 +253,9 @@ def batched_section(bsm, reps, stream):
             del outs
     del ref
     torch.cuda.empty_cache()
+    res["tuning"] = bsm.bsm_tune_get()
+    if os.path.exists(TUNED):
+        bsm.bsm_tune_load(TUNED)
     return res
 
 
