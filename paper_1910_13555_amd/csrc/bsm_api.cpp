@@ -160,6 +160,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                pl->pptr.p, pl->c_rs, pl->c_cs, pl->rowq.p, pl->nprod,
                max_tiles(ta ? A->h_cs : A->h_rs, tb ? B->h_rs : B->h_cs), pl->seg, pl->desc);
   } else if (pl->ntasks > 0) {
+    const bool split = pl->opts.precision != BSM_PREC_FP64;
     // step records (no readback: the symbolic count bounds them, tiles
     // without products add one step each)
     pl->nsteps = h[kFSteps] + pl->ntasks;
@@ -177,11 +178,11 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     pl->steps = DBuf<uint64_t>(ctx, 2 * pl->nsteps);
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
     hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
-                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, pl->steps.p,
-                                pl->sdesc.p),
+                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, split,
+                                pl->steps.p, pl->sdesc.p),
               "work items");
     hip_check(launch_product_steps(st, pl->nprod, pl->c_nblk, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
-                                   pl->c_cs, pl->px.p, pl->py.p, pl->steps.p),
+                                   pl->c_cs, pl->px.p, pl->py.p, split, pl->steps.p),
               "product steps");
   }
   // temporaries go back to the allocator: later work on this stream is ordered after the fill

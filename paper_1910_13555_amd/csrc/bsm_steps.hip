@@ -16,6 +16,22 @@ namespace {
 
 constexpr int kStepK = 16;
 
+// The two words of a step record.  FP64: byte offsets into the float64
+// values (A row-major, B row-major).  Split precision: byte offsets into the
+// bfloat16 piece arrays, A row-major, B blocks transposed (element (k, c) of
+// a K x N block at c * K + k).
+__device__ __forceinline__ void step_words(int64_t xo, int64_t yo, int K, int N, int r0, int c0, int k0,
+                                           bool split, uint64_t* out) {
+  const uint64_t kv = (uint64_t)min(kStepK, K - k0);
+  if (!split) {
+    out[0] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
+    out[1] = ((uint64_t)(yo + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
+  } else {
+    out[0] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 2u) | ((uint64_t)K << 48);
+    out[1] = ((uint64_t)(yo + (int64_t)c0 * K + k0) * 2u) | (kv << 48);
+  }
+}
+
 __global__ void k_count_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ pptr,
                               const int64_t* __restrict__ px, int64_t* __restrict__ nsteps) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,7 +124,7 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
                              const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
                              const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
                              const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, uint64_t* __restrict__ steps,
+                             const int32_t* __restrict__ cs, int split, uint64_t* __restrict__ steps,
                              TaskDesc* __restrict__ desc) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
@@ -144,11 +160,7 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
     const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
     const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
     const int K = (int)(xw >> 48);
-    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) {
-      const uint64_t kv = (uint64_t)min(kStepK, K - k0);
-      steps[2 * s] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
-      steps[2 * s + 1] = ((uint64_t)(yo + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
-    }
+    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xo, yo, K, N, r0, c0, k0, split != 0, steps + 2 * s);
   }
 }
 
@@ -158,7 +170,7 @@ __global__ void k_product_steps(int64_t nprod, int64_t nblk, const int64_t* __re
                                 const int64_t* __restrict__ chs, const int32_t* __restrict__ blk2tile,
                                 const int64_t* __restrict__ sbase, const int32_t* __restrict__ c_col,
                                 const int32_t* __restrict__ cs, const int64_t* __restrict__ px,
-                                const int64_t* __restrict__ py, uint64_t* __restrict__ steps) {
+                                const int64_t* __restrict__ py, int split, uint64_t* __restrict__ steps) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprod) return;
   int64_t lo = 0, hi = nblk - 1;      // the block t with pptr[t] <= p < pptr[t + 1]
@@ -174,11 +186,7 @@ __global__ void k_product_steps(int64_t nprod, int64_t nblk, const int64_t* __re
   const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
   const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
   const int K = (int)(xw >> 48);
-  for (int k0 = 0; k0 < K; k0 += kStepK, ++s) {
-    const uint64_t kv = (uint64_t)min(kStepK, K - k0);
-    steps[2 * s] = ((uint64_t)(xo + k0) * 8u) | ((uint64_t)K << 48);
-    steps[2 * s + 1] = ((uint64_t)(yo + (int64_t)k0 * N) * 8u) | (kv << 48);
-  }
+  for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xo, yo, K, N, 0, 0, k0, split != 0, steps + 2 * s);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -211,20 +219,20 @@ hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const 
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc) {
+                             const int32_t* rs, const int32_t* cs, bool split, uint64_t* steps, TaskDesc* desc) {
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, steps, desc);
+                     c_col, c_off, cin_off, pptr, px, py, rs, cs, (int)split, steps, desc);
   return hipGetLastError();
 }
 
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
                                 const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
                                 const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
-                                uint64_t* steps) {
+                                bool split, uint64_t* steps) {
   if (nprod == 0) return hipSuccess;
   hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, nblk, pptr,
-                     chs, blk2tile, sbase, c_col, cs, px, py, steps);
+                     chs, blk2tile, sbase, c_col, cs, px, py, (int)split, steps);
   return hipGetLastError();
 }
 
