@@ -29,6 +29,7 @@ METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B; % FP64 roofline; split vs
 PEAK_FP64 = 78.6e12       # MI355X dense FP64 (vector and matrix core), FLOP/s
 PEAK_HBM = 8.0e12         # MI355X HBM3E, B/s
 KERNEL_SRC = os.path.join(ROOT, "paper_1910_13555_amd", "csrc", "bsm_numeric_core.h")
+SEQUENTIAL = False   # --sequential: numeric kernel families one after another
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_traffic_banded.json")
 TUNED = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "banded.json")
 # numeric kernel families (bsm_ctx_launch_times order) and their names in profiler output
@@ -173,15 +174,18 @@ def time_events(fn, reps, stream):
 def roofline_section(bsm, ctx, plan, A, B, out, reps):
     """Dominant numeric kernel: its useful flops per launch over its launch
     time, both measured here (HIP events recorded by the library around each
-    of its launches, on its stream)."""
+    of its launches, on its stream).  The families run one after another for
+    this measurement, so each launch time is that kernel's own."""
     import numpy as np
     flops = family_flops(plan, A, B, bsm.bsm_tune_get())
+    ctx.set_concurrent(False)
     ctx.set_timing(True)
     times = np.zeros(5)
     for _ in range(reps):
         plan.execute(1.0, A.values, B.values, 0.0, None, out)
         times += np.asarray(ctx.launch_times())
     ctx.set_timing(False)
+    ctx.set_concurrent(not SEQUENTIAL)
     times /= reps
     k = int(np.argmax(times))
     achieved = flops[k] / (times[k] * 1e-3)
@@ -333,6 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--sequential", action="store_true",
+                    help="numeric kernel families one after another (default: concurrent on side streams)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the split-precision and batched sections")
     ap.add_argument("--rank3", action="store_true",
@@ -364,6 +370,9 @@ def main():
     A = bsm.BlockSparseMatrix.from_workload(d["A"])
     B = bsm.BlockSparseMatrix.from_workload(d["B"])
     ctx = A.pattern.ctx
+    global SEQUENTIAL
+    SEQUENTIAL = args.sequential
+    ctx.set_concurrent(not SEQUENTIAL)
     eps = d["eps"]
     stream = torch.cuda.current_stream(dev)
     if args.copy_bytes > 0:
@@ -432,6 +441,7 @@ def main():
         "numeric_only_gflops": F / (reuse_ms * 1e-3) / 1e9,
         "roofline": roofline_section(bsm, ctx, plan, A, B, out, args.steps),
         "tuning": bsm.bsm_tune_get(),
+        "concurrent_families": not SEQUENTIAL,
     }
     if not args.no_extra:
         res["split"] = split_section(bsm, ctx, A, B, eps, out, args.steps, stream)

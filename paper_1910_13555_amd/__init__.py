@@ -83,6 +83,10 @@ class Context:
         """Record HIP events around each numeric kernel launch of later executes."""
         check(lib.bsm_ctx_set_timing(self.handle, int(bool(on))))
 
+    def set_concurrent(self, on: bool):
+        """Run the numeric kernel families of one execute concurrently (default) or in sequence."""
+        check(lib.bsm_ctx_set_concurrent(self.handle, int(bool(on))))
+
     def launch_times(self):
         """Milliseconds of each numeric kernel family in the last execute (5 floats)."""
         out = (C.c_float * 5)()

@@ -84,6 +84,7 @@ PROTOTYPES = {
                           C.POINTER(MmOpts), C.POINTER(_vp)],
     "bsm_plan_t3_pattern": [_vp, C.POINTER(_vp)],
     "bsm_ctx_set_timing": [_vp, C.c_int32],
+    "bsm_ctx_set_concurrent": [_vp, C.c_int32],
     "bsm_ctx_launch_times": [_vp, C.POINTER(C.c_float)],
     "bsm_tune_load": [C.c_char_p],
     "bsm_tune_panel": [C.c_int32, C.c_int32],

@@ -246,6 +246,7 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
     P.ev = pl->ctx->ev;
     P.launched = pl->ctx->launched;
   }
+  attach_side_streams(pl->ctx, P);
   if (pl->opts.precision == BSM_PREC_FP64) hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
   else hip_check(launch_numeric_split(pl->ctx->stream, split_pieces(pl->opts.precision), P), "split numeric");
 }
@@ -449,6 +450,13 @@ bsm_status bsm_ctx_set_timing(bsm_ctx ctx, int32_t on) {
         if (!e) hip_check(hipEventCreate(&e), "event");
     std::fill(ctx->launched, ctx->launched + kNumericKernels, 0);
     ctx->timing = on != 0;
+  });
+}
+
+bsm_status bsm_ctx_set_concurrent(bsm_ctx ctx, int32_t on) {
+  return guard([&] {
+    if (!ctx) fail(BSM_E_INVALID, "NULL context");
+    ctx->concurrent = on != 0;
   });
 }
 

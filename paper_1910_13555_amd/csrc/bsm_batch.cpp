@@ -154,6 +154,7 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   P.mx = b->mx;
   P.my = b->my;
   P.mo = b->mo;
+  attach_side_streams(ctx, P);
   auto launch = [&](hipStream_t st) {
     return b->precision == BSM_PREC_FP64 ? launch_numeric(st, b->generic, P)
                                          : launch_numeric_split(st, split_pieces(b->precision), P);

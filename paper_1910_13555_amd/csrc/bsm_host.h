@@ -136,9 +136,20 @@ struct bsm_ctx_s {
   // pinned host staging for small readbacks
   static constexpr size_t kStaging = 4096;
   void* staging = nullptr;
+  // concurrent numeric kernel families (bsm_ctx_set_concurrent): side streams
+  // and the fork / join events, created on first use
+  bool concurrent = true;
+  hipStream_t side[bsm::kNumericKernels - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[bsm::kNumericKernels - 1] = {};
   ~bsm_ctx_s() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipStream_t s : side)
+      if (s) (void)hipStreamDestroy(s);
     if (staging) (void)hipHostFree(staging);
   }
 };
@@ -237,6 +248,23 @@ std::vector<T> download(bsm_ctx c, const T* d, size_t n) {
 inline void set_device(bsm_ctx c) {
   if (c->device < 0) fail(BSM_E_DEVICE, "host-only context (device -1) cannot run device work");
   hip_check(hipSetDevice(c->device), "hipSetDevice");
+}
+
+// Side streams of the numeric launches (default priority, not blocking on the
+// null stream) for a context with concurrent families; P is left alone
+// otherwise.
+inline void attach_side_streams(bsm_ctx c, NumParams& P) {
+  if (!c->concurrent) return;
+  if (!c->fork) {
+    for (auto& s : c->side)
+      if (!s) hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "side stream");
+    for (auto& e : c->join)
+      if (!e) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "event");
+  }
+  P.side = c->side;
+  P.fork = c->fork;
+  P.join = c->join;
 }
 
 }  // namespace

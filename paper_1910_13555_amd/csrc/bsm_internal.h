@@ -109,6 +109,11 @@ struct NumParams {
   int32_t has_cin = 0;            // batches: some problem adds beta * C_in
   hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
   int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran
+  // optional: side streams (kNumericKernels - 1) on which families after the
+  // first run concurrently, forked after `fork` and joined through join[i]
+  const hipStream_t* side = nullptr;
+  hipEvent_t fork = nullptr;
+  const hipEvent_t* join = nullptr;
 };
 constexpr int kNumericKernels = 5;  // FP64 numeric kernel families (4x4x4: <=16, 24, 32 wide; 16x16x4: 16, 32)
 

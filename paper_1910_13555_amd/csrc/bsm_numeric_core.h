@@ -665,31 +665,54 @@ ClassWaves class_waves(const NumParams& p, int kid, int resident) {
   return cw;
 }
 
+// One persistent launch per kernel family with work.  With side streams the
+// families after the first run concurrently with it: each persistent grid
+// fills the device on its own, so a later family's waves take the compute
+// units that an earlier family's finished waves free, instead of every
+// family ending in its own tail.  Tiles are disjoint across families, so the
+// result does not depend on the overlap.
 template <bool GEN, bool CIN, bool BATCH>
 hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
+  ClassWaves cw[kKernels];
+  int nfam = 0;
+  for (int kid = 0; kid < kKernels; ++kid) {
+    cw[kid] = class_waves(p, kid, p.ncu * 4 * kKernWaves[kid]);
+    nfam += cw[kid].w[kClasses] > 0;
+  }
+  const bool conc = p.side && nfam > 1;
+  hipError_t e;
+  if (conc && (e = hipEventRecord(p.fork, s)) != hipSuccess) return e;
+  int nside = 0;
+  bool first = true;
   for (int kid = kKernels - 1; kid >= 0; --kid) {
-    const ClassWaves cw = class_waves(p, kid, p.ncu * 4 * kKernWaves[kid]);
-    const int W = cw.w[kClasses];
+    const int W = cw[kid].w[kClasses];
     if (W == 0) continue;
-    if (p.ev) {
-      const hipError_t e = hipEventRecord(p.ev[2 * kid], s);
-      if (e != hipSuccess) return e;
+    hipStream_t ls = s;
+    if (conc && !first) {  // at most kKernels - 1 families after the first
+      ls = p.side[nside];
+      if ((e = hipStreamWaitEvent(ls, p.fork, 0)) != hipSuccess) return e;
     }
+    first = false;
+    if (p.ev && (e = hipEventRecord(p.ev[2 * kid], ls)) != hipSuccess) return e;
     switch (kid) {
-      case 0: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 0>), dim3(W), dim3(64), 0, s, p, cw); break;
-      case 1: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 1>), dim3(W), dim3(64), 0, s, p, cw); break;
-      case 2: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 2>), dim3(W), dim3(64), 0, s, p, cw); break;
-      case 3: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 3>), dim3(W), dim3(64), 0, s, p, cw); break;
-      default: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 4>), dim3(W), dim3(64), 0, s, p, cw); break;
+      case 0: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 0>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
+      case 1: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 1>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
+      case 2: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 2>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
+      case 3: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 3>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
+      default: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 4>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (p.ev) {
-      e = hipEventRecord(p.ev[2 * kid + 1], s);
-      if (e != hipSuccess) return e;
+      if ((e = hipEventRecord(p.ev[2 * kid + 1], ls)) != hipSuccess) return e;
       p.launched[kid] = 1;
     }
+    if (ls != s) {
+      if ((e = hipEventRecord(p.join[nside], ls)) != hipSuccess) return e;
+      ++nside;
+    }
   }
+  for (int i = 0; i < nside; ++i)
+    if ((e = hipStreamWaitEvent(s, p.join[i], 0)) != hipSuccess) return e;
   return hipSuccess;
 }
 

@@ -97,6 +97,46 @@ def test_graph_replays(bsm):
     batch.close()
 
 
+def test_concurrent_families_bit_identical(bsm):
+    """Kernel families on side streams (the default) and one after another on
+    the context's stream give bit-identical outputs, eager and in a graph
+    replayed several times."""
+    probs = workloads.batched(nprob=8, seed_tag=15, nmin=10, nmax=80)
+    ctx = bsm.default_context()
+    mats, plans, cins = setup(bsm, probs, ctx, with_c=True, seed=3)
+    a = [m[0].values for m in mats]
+    b = [m[1].values for m in mats]
+    betas = [0.5] * len(probs)
+    try:
+        ctx.set_concurrent(False)
+        batch = bsm.bsm_batch_create(ctx, plans)
+        ref = [t.clone() for t in batch.execute(1.5, a, b, betas, cins)]
+        single = [p.execute(1.5, m[0].values, m[1].values, 0.5, ci).clone()
+                  for p, m, ci in zip(plans, mats, cins)]
+        batch.close()
+        torch.cuda.synchronize()
+        ctx.set_concurrent(True)
+        batch = bsm.bsm_batch_create(ctx, plans)
+        eager = batch.execute(1.5, a, b, betas, cins)
+        torch.cuda.synchronize()
+        for r, t in zip(ref, eager):
+            assert torch.equal(r, t)
+        outs = [torch.empty_like(t) for t in ref]
+        for rep in range(3):
+            for t in outs:
+                t.fill_(float("nan"))
+            batch.execute(1.5, a, b, betas, cins, out=outs, use_graph=True)
+            torch.cuda.synchronize()
+            for r, t in zip(ref, outs):
+                assert torch.equal(r, t), f"replay {rep} differs"
+        for p, m, ci, r in zip(plans, mats, cins, single):
+            assert torch.equal(p.execute(1.5, m[0].values, m[1].values, 0.5, ci), r)
+        batch.close()
+    finally:
+        ctx.set_concurrent(True)
+    oracle_check(probs, mats, plans, ref, [1.5] * len(probs), betas)
+
+
 def test_batch_rejects_bad_input(bsm):
     ctx = bsm.default_context()
     rng = np.random.default_rng(14)
