@@ -162,8 +162,9 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
   } else if (pl->ntasks > 0) {
     const bool split = pl->opts.precision != BSM_PREC_FP64;
     // step records (no readback: the symbolic count bounds them, tiles
-    // without products add one step each)
-    pl->nsteps = h[kFSteps] + pl->ntasks;
+    // without products add one step each, split plans one padding step per
+    // tile at most)
+    pl->nsteps = h[kFSteps] + (split ? 2 : 1) * pl->ntasks;
     if (pl->nsteps >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 product steps");
     DBuf<int64_t> ch(ctx, pl->nprod + 1), chs(ctx, pl->nprod + 2), ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1);
     DBuf<int32_t> b2t(ctx, pl->c_nblk);
@@ -171,15 +172,15 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     DBuf<int64_t> scr1(ctx, scan_scratch_size(1, std::max<int64_t>(pl->nprod, 1)));
     hip_check(launch_scan(st, 1, pl->nprod, ch.p, chs.p, nullptr, scr1.p), "chunk scan");
     hip_check(launch_tile_steps(st, (int32_t)pl->ntasks, pl->c_nblk, pl->tasks.p, pl->pptr.p, chs.p, pl->c_row.p,
-                                pl->c_col.p, pl->c_rs, pl->c_cs, ns.p, b2t.p),
+                                pl->c_col.p, pl->c_rs, pl->c_cs, split, ns.p, b2t.p),
               "tile steps");
     DBuf<int64_t> scr2(ctx, scan_scratch_size(1, pl->ntasks));
     hip_check(launch_scan(st, 1, pl->ntasks, ns.p, sb.p, nullptr, scr2.p), "step scan");
     pl->steps = DBuf<uint64_t>(ctx, 2 * pl->nsteps);
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
     hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
-                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, split,
-                                pl->steps.p, pl->sdesc.p),
+                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, chs.p,
+                                split, pl->steps.p, pl->sdesc.p),
               "work items");
     hip_check(launch_product_steps(st, pl->nprod, pl->c_nblk, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
                                    pl->c_cs, pl->px.p, pl->py.p, split, pl->steps.p),
@@ -247,8 +248,28 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
     P.launched = pl->ctx->launched;
   }
   attach_side_streams(pl->ctx, P);
-  if (pl->opts.precision == BSM_PREC_FP64) hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
-  else hip_check(launch_numeric_split(pl->ctx->stream, split_pieces(pl->opts.precision), P), "split numeric");
+  if (pl->opts.precision == BSM_PREC_FP64) {
+    hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
+    return;
+  }
+  // split precision: piece arrays of both operands (freed to the context's
+  // allocator after the launch; later work on the stream is ordered after it)
+  const int np = split_pieces(pl->opts.precision);
+  hipStream_t st = pl->ctx->stream;
+  bsm_pattern A = pl->A, B = pl->B;
+  const int64_t sx = piece_stride(A->nvals), sy = piece_stride(B->nvals);
+  DBuf<uint16_t> xp(pl->ctx, (size_t)np * sx), yp(pl->ctx, (size_t)np * sy);
+  if (pl->nprod > 0) {  // else every tile is empty and no operand is read
+    hip_check(launch_split_rows(st, np, x, A->nvals, sx, xp.p), "split A");
+    hip_check(launch_split_cols(st, np, y, B->nblk, B->d_row.p, B->d_col.p, B->h_blk.empty() ? nullptr : B->d_blk.p,
+                                B->d_off.p, B->d_rs.p, B->d_cs.p, B->nvals, sy, yp.p),
+              "split B");
+  }
+  P.X = reinterpret_cast<const double*>(xp.p);
+  P.Y = reinterpret_cast<const double*>(yp.p);
+  P.xpb = (uint32_t)(2 * sx);
+  P.ypb = (uint32_t)(2 * sy);
+  hip_check(launch_numeric_split(st, np, P), "split numeric");
 }
 
 template <class G>
@@ -534,6 +555,9 @@ bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals, c
     if (A->ctx != ctx) fail(BSM_E_INVALID, "pattern of another context");
     if (o.precision != BSM_PREC_FP64 && (o.trans_a || o.trans_b))
       fail(BSM_E_UNSUPPORTED, "split precision needs untransposed operands");
+    if (o.precision != BSM_PREC_FP64 &&
+        (piece_stride(A->nvals) >= (int64_t(1) << 30) || piece_stride(B->nvals) >= (int64_t(1) << 30)))
+      fail(BSM_E_UNSUPPORTED, "split precision: operands of at most 2^30 - 80 values");
     set_device(ctx);
     auto pl = std::make_unique<bsm_plan_s>();
     pl->ctx = ctx;

@@ -3,6 +3,8 @@
 // run by one persistent launch per kernel size group; a per-problem table
 // gives each work item its buffers and scalars.  With use_graph the launch is
 // captured into a HIP graph once and replayed while the table is unchanged.
+// Split-precision batches own the piece arrays of every problem's operands
+// and split them ahead of the numeric launch (inside the graph, too).
 #include "bsm_host.h"
 
 using namespace bsm;
@@ -19,6 +21,12 @@ struct bsm_batch_s {
   int32_t cls_tile[kClasses + 1] = {0};
   DBuf<ProbPtrs> ptab;
   std::vector<ProbPtrs> hptab;
+  // split precision: piece arrays (problem p: A pieces from xoff[p], stride
+  // sx[p]; B pieces from yoff[p], stride sy[p]) and the operand pointers
+  // they were split from by the current graph
+  DBuf<uint16_t> pieces;
+  std::vector<int64_t> xoff, yoff, sx, sy;
+  std::vector<const double*> ua, ub;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraph_t graph = nullptr;
@@ -104,6 +112,19 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
     hip_check(launch_merge_desc(st, b->steps ? b->plans[p]->sdesc.p : b->plans[p]->desc.p, rng[p], p, b->desc.p),
               "merge work items");
   b->ptab = DBuf<ProbPtrs>(ctx, n);
+  if (b->precision != BSM_PREC_FP64) {
+    const int np = split_pieces(b->precision);
+    int64_t at = 0;
+    for (int32_t p = 0; p < n; ++p) {
+      b->sx.push_back(piece_stride(b->plans[p]->A->nvals));
+      b->sy.push_back(piece_stride(b->plans[p]->B->nvals));
+      b->xoff.push_back(at);
+      at += np * b->sx.back();
+      b->yoff.push_back(at);
+      at += np * b->sy.back();
+    }
+    b->pieces = DBuf<uint16_t>(ctx, (size_t)at);
+  }
   hip_check(hipStreamSynchronize(st), "batch setup");
   return b.release();
 }
@@ -113,6 +134,7 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   if (!alpha || !beta || !a || !bv || !out) fail(BSM_E_INVALID, "NULL argument array");
   bsm_ctx ctx = b->ctx;
   const int32_t n = (int32_t)b->plans.size();
+  const bool split = b->precision != BSM_PREC_FP64;
   std::vector<ProbPtrs> t(n);
   for (int32_t p = 0; p < n; ++p) {
     bsm_plan pl = b->plans[p];
@@ -133,11 +155,23 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
     t[p].inplace_skip = (out[p] == ci && beta[p] == 1.0) ? 1 : 0;
     t[p].pad = 0;
     t[p].steps = b->steps ? pl->steps.p : nullptr;
-    t[p].pad2 = nullptr;
+    t[p].xpb = 0;
+    t[p].ypb = 0;
+    if (split) {  // the kernel reads the piece arrays
+      t[p].X = reinterpret_cast<const double*>(b->pieces.p + b->xoff[p]);
+      t[p].Y = reinterpret_cast<const double*>(b->pieces.p + b->yoff[p]);
+      t[p].xpb = (uint32_t)(2 * b->sx[p]);
+      t[p].ypb = (uint32_t)(2 * b->sy[p]);
+    }
   }
   set_device(ctx);
   bool changed = b->hptab.size() != t.size();
   for (int32_t p = 0; !changed && p < n; ++p) changed = !same_ptrs(t[p], b->hptab[p]);
+  if (split && !changed) changed = !std::equal(a, a + n, b->ua.begin()) || !std::equal(bv, bv + n, b->ub.begin());
+  if (split) {
+    b->ua.assign(a, a + n);
+    b->ub.assign(bv, bv + n);
+  }
   if (changed) {
     hip_check(hipMemcpyAsync(b->ptab.p, t.data(), sizeof(ProbPtrs) * n, hipMemcpyHostToDevice, ctx->stream),
               "problem table");
@@ -156,8 +190,21 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   P.mo = b->mo;
   attach_side_streams(ctx, P);
   auto launch = [&](hipStream_t st) {
-    return b->precision == BSM_PREC_FP64 ? launch_numeric(st, b->generic, P)
-                                         : launch_numeric_split(st, split_pieces(b->precision), P);
+    if (!split) return launch_numeric(st, b->generic, P);
+    const int np = split_pieces(b->precision);
+    for (int32_t p = 0; p < n; ++p) {
+      bsm_plan pl = b->plans[p];
+      if (pl->nprod == 0) continue;
+      uint16_t* xp = b->pieces.p + b->xoff[p];
+      uint16_t* yp = b->pieces.p + b->yoff[p];
+      bsm_pattern B = pl->B;
+      hipError_t e = launch_split_rows(st, np, a[p], pl->A->nvals, b->sx[p], xp);
+      if (e == hipSuccess)
+        e = launch_split_cols(st, np, bv[p], B->nblk, B->d_row.p, B->d_col.p, B->h_blk.empty() ? nullptr : B->d_blk.p,
+                              B->d_off.p, B->d_rs.p, B->d_cs.p, B->nvals, b->sy[p], yp);
+      if (e != hipSuccess) return e;
+    }
+    return launch_numeric_split(st, np, P);
   };
   if (!use_graph) {
     hip_check(launch(ctx->stream), "batch numeric");

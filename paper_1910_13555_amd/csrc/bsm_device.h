@@ -61,7 +61,7 @@ __device__ __forceinline__ ProbPtrs prob(const NumParams& P, int pid) {
     ProbPtrs q;
     q.out = P.out; q.cin = P.cin; q.X = P.X; q.Y = P.Y; q.px = P.px; q.py = P.py;
     q.alpha = P.alpha; q.beta = P.beta; q.inplace_skip = P.inplace_skip; q.pad = 0;
-    q.steps = P.steps; q.pad2 = nullptr;
+    q.steps = P.steps; q.xpb = P.xpb; q.ypb = P.ypb;
     return q;
   }
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -72,7 +72,7 @@ __device__ __forceinline__ ProbPtrs prob(const NumParams& P, int pid) {
   ProbPtrs q;
   q.out = P.out; q.cin = P.cin; q.X = P.X; q.Y = P.Y; q.px = P.px; q.py = P.py;
   q.alpha = P.alpha; q.beta = P.beta; q.inplace_skip = P.inplace_skip; q.pad = 0;
-  q.steps = P.steps; q.pad2 = nullptr;
+  q.steps = P.steps; q.xpb = P.xpb; q.ypb = P.ypb;
   return q;
 }
 

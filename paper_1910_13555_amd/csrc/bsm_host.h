@@ -430,9 +430,8 @@ struct bsm_plan_s {
   DBuf<uint64_t> steps;
   DBuf<TaskDesc> sdesc;
   int64_t nsteps = 0;
-  bool step_path() const {
-    return opts.precision == BSM_PREC_FP64 && mx == bsm::kRowMajor && my == bsm::kRowMajor &&
-           mo == bsm::kRowMajor && !rowq.p;
+  bool step_path() const {  // row-major operands and output (FP64 or split precision)
+    return mx == bsm::kRowMajor && my == bsm::kRowMajor && mo == bsm::kRowMajor && !rowq.p;
   }
   DBuf<int32_t> rowq;  // split factors for tensor layouts (optional)
   DBuf<double> na, nb; // stored-block norms of A and B (kept for the gradient when filtering)

@@ -87,7 +87,7 @@ struct ProbPtrs {
   double alpha, beta;
   int32_t inplace_skip, pad;
   const uint64_t* steps;  // step records (row-major path)
-  const void* pad2;
+  uint32_t xpb, ypb;      // split precision: X / Y are piece arrays of this many bytes each
 };
 
 struct NumParams {
@@ -107,6 +107,7 @@ struct NumParams {
   int32_t mx = kRowMajor, my = kRowMajor, mo = kRowMajor;
   int32_t inplace_skip = 0;       // out == cin, beta == 1: blocks without products untouched
   int32_t has_cin = 0;            // batches: some problem adds beta * C_in
+  uint32_t xpb = 0, ypb = 0;      // split precision: X / Y are piece arrays of this many bytes each
   hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
   int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran
   // optional: side streams (kNumericKernels - 1) on which families after the
@@ -172,11 +173,12 @@ hipError_t launch_fill_steps(hipStream_t s, int32_t ntiles, const int2* tiles, c
 hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, int64_t* chunks);
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
                              const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
-                             const int32_t* cs, int64_t* nsteps, int32_t* blk2tile);
+                             const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile);
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, bool split, uint64_t* steps, TaskDesc* desc);
+                             const int32_t* rs, const int32_t* cs, const int64_t* chs, bool split, uint64_t* steps,
+                             TaskDesc* desc);
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
                                 const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
                                 const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
@@ -188,9 +190,21 @@ hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);
 // (0: FP64 4x4x4, 1: FP64 16x16x4); set_variants rejects other values.
 void get_variants(int32_t* out16);
 bool set_variants(const int32_t* in16);
-// bsm_split.hip: split-precision numeric phase (row-major operands only),
-// npieces bfloat16 pieces per value (2: bf16x3, 3: bf16x6).
+// bsm_split.hip: split-precision numeric phase on step records (row-major
+// operands only), npieces bfloat16 pieces per value (2: bf16x3, 3: bf16x6).
+// X / Y of p are the piece arrays (p.xpb / p.ypb bytes per piece).
 hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p);
+// Piece arrays: piece p of n values at out + p * stride, elements [n, stride)
+// zero.  Rows: the values' own order (stride a multiple of 4).  Cols: every
+// block of a pattern (entries row/col, stored index blk or identity, stored
+// offsets off, block sizes rs/cs) transposed.
+hipError_t launch_split_rows(hipStream_t s, int npieces, const double* x, int64_t n, int64_t stride, uint16_t* out);
+hipError_t launch_split_cols(hipStream_t s, int npieces, const double* y, int64_t nblk, const int32_t* row,
+                             const int32_t* col, const int32_t* blk, const int64_t* off, const int32_t* rs,
+                             const int32_t* cs, int64_t n, int64_t stride, uint16_t* out);
+// Elements per piece array of n values (zero tail of at least 16: a lane's
+// 16-byte load never straddles the array's end).
+inline int64_t piece_stride(int64_t n) { return ((n + 16 + 63) / 64) * 64; }
 inline int split_pieces(int precision) { return precision == 2 ? 3 : 2; }
 // Batches: copy one plan's work items (class c at [sbeg[c], sbeg[c+1])) to
 // dbeg[c] of a merged list, tagged with problem pid.

@@ -1,20 +1,27 @@
 // Split-precision numeric phase (an optional mode; the paper computes in
-// double only, Sec. 3).  Same work items as the FP64 kernels (output tiles of
-// at most 32 x 32 with segments of at most 64 products, k concatenated across
-// a segment's products), but the products run on the bfloat16 matrix cores:
-// every operand value is rounded to float32 (nearest even) and cut into
-// bfloat16 pieces h, m, l (each nearest even, the remainders exact in
-// float32); a block product becomes
+// double only, Sec. 3).  Every operand value is rounded to float32 (nearest
+// even) and cut into bfloat16 pieces h, m, l (each nearest even, the
+// remainders exact in float32); a block product becomes
 //     bf16x3:  Ah.Bh + Ah.Bl + Al.Bh                          (two pieces)
 //     bf16x6:  Ah.Bh + Ah.Bm + Am.Bh + Am.Bm + Ah.Bl + Al.Bh  (three pieces)
-// Piece products are exact in float32; the 16x16x32 instruction sums one
-// chunk of 32 concatenated k in float32, and each chunk's sum is added into a
-// float64 accumulator, so float32 rounding is confined to one chunk.  alpha,
-// beta, C_in and the output stay float64, as do the norms and the filter of
-// the symbolic phase.
+// on the bfloat16 matrix cores.  Piece products are exact in float32; the
+// instruction chain of a tile accumulates its whole product run in float32,
+// and the sum goes into the float64 output once: C = beta C_in + alpha sum.
+// alpha, beta, C_in, the output, the norms and the filter of the symbolic
+// phase stay float64.
 //
-// Tiles pad to multiples of 16 (the instruction's 16 x 16 output).  Row-major
-// operands only (no transposition, no tensor layouts).
+// Two passes per execute:
+//  1. the operands are split once into piece arrays (A: the values' own
+//     element order; B: every block transposed, element (k, c) of a K x N
+//     block at offset + c K + k), so that the 8 consecutive k a lane feeds to
+//     the 16x16x32 instruction are one 16-byte load;
+//  2. the persistent kernel walks the step records of the row-major path (one
+//     work item per output tile, a step = one product's k range of 16), two
+//     steps per instruction: lanes 0-31 carry the even step of a pair, lanes
+//     32-63 the odd one (each tile's step list has even length).  Slots past
+//     a step's valid k, rows past the tile and columns past the tile read
+//     zero.
+// Row-major operands and output only (no transposition, no tensor layouts).
 #include "bsm_device.h"
 
 namespace bsm {
@@ -24,22 +31,9 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
 
-constexpr int SKC = 32;          // k per chunk: one instruction deep
-constexpr int SLD = SKC + 8;     // staged row stride in bfloat16 (80 bytes, 16-byte aligned)
-constexpr int kSplitWaves = 2;   // resident wavefronts per SIMD (register budget)
-
-template <int NP>
-struct SplitStage {
-  alignas(16) uint16_t A[NP][kTile * SLD];   // pieces of the A tile, [row][k]
-  alignas(16) uint16_t B[NP][kTile * SLD];   // pieces of the B tile, [column][k]
-  Rec rec[kSeg];
-  // per slot: address of the slot's element in the tile's first row of the A
-  // block (-1: empty slot), the A block's row stride, address of the slot's
-  // row of the B block at the tile's first column
-  int64_t a0[2][SKC], b0[2][SKC];
-  int32_t ak[2][SKC];
-};
+constexpr uint32_t kOobS = 0x80000000u;   // an offset past every piece array (< 2 GB each)
 
 // Round to nearest even, float32 -> bfloat16 bits (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
@@ -61,6 +55,61 @@ __device__ __forceinline__ void split_value(double x, uint32_t (&p)[NP]) {
   }
 }
 
+// ------------------------------------------------------------ piece arrays
+
+// Pieces of n values in their own order, four per thread; piece p at
+// out + p * stride; elements [n, stride) are zero (stride: a multiple of 4).
+template <int NP>
+__global__ void k_split_rows(const double* __restrict__ x, int64_t n, int64_t stride, uint16_t* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i0 = 4 * q;
+  if (i0 >= stride) return;
+  uint32_t pc[4][NP];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) split_value<NP>(i0 + j < n ? x[i0 + j] : 0.0, pc[j]);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    uint2 v;
+    v.x = pc[0][p] | (pc[1][p] << 16);
+    v.y = pc[2][p] | (pc[3][p] << 16);
+    *reinterpret_cast<uint2*>(out + p * stride + i0) = v;
+  }
+}
+
+// Pieces of the blocks of a pattern, each K x N block transposed; one
+// wavefront per block entry.  Elements [n, stride) of each piece are
+// written by k_split_tail.
+template <int NP>
+__global__ void k_split_cols(const double* __restrict__ y, int64_t nblk, const int32_t* __restrict__ row,
+                             const int32_t* __restrict__ col, const int32_t* __restrict__ blk,
+                             const int64_t* __restrict__ off, const int32_t* __restrict__ rs,
+                             const int32_t* __restrict__ cs, int64_t stride, uint16_t* __restrict__ out) {
+  const int l = threadIdx.x % kWave;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; e < nblk; e += nw) {
+    const int64_t o = off[blk ? blk[e] : e];
+    const int K = rs[row[e]], N = cs[col[e]];
+    const int64_t KN = (int64_t)K * N;
+    for (int64_t idx = l; idx < KN; idx += kWave) {
+      const int64_t k = idx / N, c = idx - k * N;
+      uint32_t pc[NP];
+      split_value<NP>(y[o + idx], pc);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) out[p * stride + o + (int64_t)c * K + k] = (uint16_t)pc[p];
+    }
+  }
+}
+
+__global__ void k_split_tail(int npieces, int64_t n, int64_t stride, uint16_t* __restrict__ out) {
+  const int64_t t = stride - n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npieces * t) return;
+  const int64_t p = i / t;
+  out[p * stride + n + (i - p * t)] = 0;
+}
+
+// ------------------------------------------------------------ numeric kernel
+
 // Cross products of pieces (left, right), smallest first.
 template <int NP>
 struct Terms;
@@ -77,204 +126,200 @@ struct Terms<3> {
   static constexpr int b[6] = {0, 2, 1, 0, 1, 0};
 };
 
-// Pipelined loop over work items [t_begin, t_end) of one tile class, padded
-// to MX x MY instructions of 16 x 16.  Gather layout: A slot l % 32, rows
-// 2s + l / 32; B element s * 64 + l = (kk, c) with c fastest.
-template <int MX, int MY, int NP>
-__device__ void run_split(const NumParams& P, SplitStage<NP>& S, int t_begin, int t_end) {
-  constexpr int TN = 16 * MY;
-  constexpr int SA = 8 * MX, SB = 8 * MY;
-  const int l = threadIdx.x;
+__device__ __forceinline__ u32x4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t piece_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
 
-  auto load_recs = [&](int t, int64_t& xw, int64_t& yw) {
-    const TaskDesc d = desc_at(P, t);
-    const ProbPtrs pp = prob(P, d.pid);
-    xw = 0;
-    yw = 0;
-    if (l < d.np) { xw = pp.px[d.pbeg + l]; yw = pp.py[d.pbeg + l]; }
+// Loop over this wavefront's tiles of one class, MX x MY instructions of
+// 16 x 16 per tile, D pairs of steps in flight.  Records: lane l reads the
+// record of step 2 j + l / 32 of its pair j.
+template <int MX, int MY, int NP, bool CIN, bool BATCH, int D>
+__device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int e1, int r, int stride) {
+  const int l = threadIdx.x;
+  const int l16 = l & 15;            // row of A / column of B inside an instruction tile
+  const int h = (l >> 4) & 1;        // k half (8 values) of the lane's step
+  const int sp = l >> 5;             // step of the pair
+
+  int it = e0 + r;
+  if (it >= e1) return;
+
+  // ---- record cursor, D pairs ahead of the issue cursor
+  TaskDesc pdn = desc_at(P, it);
+  int pt = it, ps = (int)pdn.pbeg, pe = ps + pdn.np;
+  const uint64_t* psteps = BATCH ? prob<BATCH>(P, pdn.pid).steps : P.steps;
+  const uint64_t* const first_rec = psteps + 2 * (int64_t)ps;
+  bool plive = true;
+  if (pt + stride < e1) pdn = desc_at(P, pt + stride);
+  auto load_rec = [&]() __attribute__((always_inline)) {
+    const uint64_t* q = plive ? psteps + 2 * (int64_t)(ps + sp) : first_rec;
+    return *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(gptr(q));
   };
-  auto publish_recs = [&](int64_t xw, int64_t yw) {
-    const int K = (int)((uint64_t)xw >> 48);
-    const int incl = wave_incl_scan(K);
-    Rec r;
-    r.xo = (int64_t)((uint64_t)xw & kMask48);
-    r.yo = (int64_t)((uint64_t)yw & kMask48);
-    r.K = K;
-    r.kb = incl - K;
-    r.q = 1;
-    r.pad = 0;
-    S.rec[l] = r;
-    const int total = __shfl(incl, kWave - 1, kWave);
-    return max(1, (total + SKC - 1) / SKC);
+  auto padvance = [&]() __attribute__((always_inline)) {
+    if (!plive) return;
+    ps += 2;
+    if (ps < pe) return;
+    pt += stride;
+    if (pt >= e1) {
+      plive = false;
+      return;
+    }
+    if (BATCH) psteps = prob<BATCH>(P, pdn.pid).steps;
+    ps = (int)pdn.pbeg;
+    pe = ps + pdn.np;
+    if (pt + stride < e1) pdn = desc_at(P, pt + stride);
   };
-  auto build_tab = [&](int buf, int c, const TaskDesc& d) {
-    if (l < SKC) {
-      const int k = c * SKC + l;
-      int64_t a0 = -1, b0 = -1;
-      int32_t ak = 1;
-      if (d.np > 0) {
-        int lo = 0, hi = d.np - 1;           // last product with kb <= k
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (S.rec[mid].kb <= k) lo = mid; else hi = mid - 1;
-        }
-        const Rec& r = S.rec[lo];
-        const int kq = k - r.kb;
-        if (kq < r.K) {
-          a0 = r.xo + (int64_t)(d.tr * kTile) * r.K + kq;
-          ak = r.K;
-          b0 = r.yo + (int64_t)kq * d.N + d.tc * kTile;
-        }
+
+  // ---- issue cursor: tile it, pair starting at step s of [s, se)
+  TaskDesc id = desc_at(P, it);
+  TaskDesc nd = id;
+  if (it + stride < e1) nd = desc_at(P, it + stride);
+  int s = (int)id.pbeg, se = s + id.np;
+  __amdgpu_buffer_rsrc_t ra[NP], rb[NP];
+  int rowA[MX], colB[MY];
+  auto enter = [&](const TaskDesc& d) __attribute__((always_inline)) {
+    const ProbPtrs pp = prob<BATCH>(P, d.pid);
+    const char* xa = reinterpret_cast<const char*>(pp.X);
+    const char* yb = reinterpret_cast<const char*>(pp.Y);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      ra[p] = piece_rsrc(xa + (size_t)p * pp.xpb, pp.xpb);
+      rb[p] = piece_rsrc(yb + (size_t)p * pp.ypb, pp.ypb);
+    }
+    const int mt = min(kTile, (int)d.M - d.tr * kTile), nt = min(kTile, (int)d.N - d.tc * kTile);
+#pragma unroll
+    for (int x = 0; x < MX; ++x) rowA[x] = 16 * x + l16 < mt ? 16 * x + l16 : -1;
+#pragma unroll
+    for (int y = 0; y < MY; ++y) colB[y] = 16 * y + l16 < nt ? 16 * y + l16 : -1;
+  };
+  enter(id);
+
+  u32x4 A[D][MX][NP], B[D][MY][NP];
+  u32x4 R[D];
+  int tflag[D], tpid[D], tmn[D], ttile[D];
+  int64_t tcout[D], tcin[D];
+
+  auto issue = [&](u32x4 (&a)[MX][NP], u32x4 (&b)[MY][NP], u32x4& rec, int& flag, int& pid, int& mn, int& tile,
+                   int64_t& cout, int64_t& cin) __attribute__((always_inline)) {
+    const bool live = it < e1;
+    const uint64_t w0 = ((uint64_t)rec[1] << 32) | rec[0];
+    const uint64_t w1 = ((uint64_t)rec[3] << 32) | rec[2];
+    rec = load_rec();
+    padvance();
+    const int K2 = (int)(w0 >> 48) * 2;
+    const int kv = live ? (int)(w1 >> 48) : 0;
+    const int cnt = min(max(kv - 8 * h, 0), 8);
+    // dword j holds the lane's values 2j, 2j + 1 (low half first)
+    uint32_t m[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m[j] = cnt >= 2 * j + 2 ? 0xffffffffu : (cnt == 2 * j + 1 ? 0x0000ffffu : 0u);
+    const uint32_t ao = (uint32_t)(w0 & kMask48) + 16u * h;
+    const uint32_t bo = (uint32_t)(w1 & kMask48) + 16u * h;
+#pragma unroll
+    for (int x = 0; x < MX; ++x) {
+      const uint32_t o = (rowA[x] >= 0 && cnt > 0) ? ao + (uint32_t)(rowA[x] * K2) : kOobS;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        u32x4 v = load16(ra[p], o);
+        v[0] &= m[0]; v[1] &= m[1]; v[2] &= m[2]; v[3] &= m[3];
+        a[x][p] = v;
       }
-      S.a0[buf][l] = a0;
-      S.ak[buf][l] = ak;
-      S.b0[buf][l] = b0;
     }
+#pragma unroll
+    for (int y = 0; y < MY; ++y) {
+      const uint32_t o = (colB[y] >= 0 && cnt > 0) ? bo + (uint32_t)(colB[y] * K2) : kOobS;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        u32x4 v = load16(rb[p], o);
+        v[0] &= m[0]; v[1] &= m[1]; v[2] &= m[2]; v[3] &= m[3];
+        b[y][p] = v;
+      }
+    }
+    const bool last = s + 2 >= se;
+    flag = live ? (1 | (last ? 2 : 0)) : 0;
+    pid = id.pid;
+    mn = (int)id.M | ((int)id.N << 16);
+    tile = (int)id.tr | ((int)id.tc << 16) | ((id.flags & kTaskEmpty) ? (1 << 31) : 0);
+    cout = id.cout;
+    cin = id.cin;
+    if (!live) return;
+    s += 2;
+    if (s < se) return;
+    it += stride;
+    if (it >= e1) return;
+    id = nd;
+    s = (int)id.pbeg;
+    se = s + id.np;
+    enter(id);
+    if (it + stride < e1) nd = desc_at(P, it + stride);
   };
-  double ga[SA], gb[SB];
-  auto gather = [&](int buf, const TaskDesc& d) {
-    const int r0 = d.tr * kTile, c0 = d.tc * kTile;
-    const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
-    const ProbPtrs pp = prob(P, d.pid);
-    const int64_t a0 = S.a0[buf][l % SKC];
-    const int64_t ak = S.ak[buf][l % SKC];
-    const double* xa = pp.X + a0 + (l / SKC) * ak;
-#pragma unroll
-    for (int s = 0; s < SA; ++s) {
-      const int r = 2 * s + l / SKC;
-      ga[s] = (a0 >= 0 && r < mt) ? xa[2 * s * ak] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      const int idx = s * kWave + l;
-      const int kk = idx / TN, c = idx % TN;
-      const int64_t b0 = S.b0[buf][kk];
-      gb[s] = (b0 >= 0 && c < nt) ? pp.Y[b0 + c] : 0.0;
-    }
-  };
-  auto stage = [&]() {
-#pragma unroll
-    for (int s = 0; s < SA; ++s) {
-      uint32_t pc[NP];
-      split_value<NP>(ga[s], pc);
-      const int at = (2 * s + l / SKC) * SLD + l % SKC;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) S.A[p][at] = (uint16_t)pc[p];
-    }
-#pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      uint32_t pc[NP];
-      split_value<NP>(gb[s], pc);
-      const int idx = s * kWave + l;
-      const int at = (idx % TN) * SLD + idx / TN;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) S.B[p][at] = (uint16_t)pc[p];
-    }
-  };
-  // 16x16x32 instruction: lane l holds row (A) / column (B) l % 16 at
-  // k = 8 (l / 16) .. + 7; result element e of lane l is (4 (l / 16) + e, l % 16).
-  double acc[MX][MY][4];
+
+  f32x4 acc[MX][MY];
 #pragma unroll
   for (int x = 0; x < MX; ++x)
 #pragma unroll
-    for (int y = 0; y < MY; ++y)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[x][y][e] = 0.0;
-  auto mma = [&]() {
-    bf16x8 a[NP][MX], b[NP][MY];
-    const int kofs = 8 * (l / 16);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
+    for (int y = 0; y < MY; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // result element e of lane l: row 4 (l / 16) + e, column l % 16
+  auto epilogue = [&](int pid, int mn, int tile, int64_t cout, int64_t cin) __attribute__((always_inline)) {
+    const int M = mn & 0xffff, N = mn >> 16;
+    const int er0 = (tile & 0xffff) * kTile, ec0 = ((tile >> 16) & 0x7fff) * kTile;
+    const int emt = min(kTile, M - er0), ent = min(kTile, N - ec0);
+    const ProbPtrs pp = prob<BATCH>(P, pid);
+    if (!(pp.inplace_skip && tile < 0)) {
+      const uint32_t bytes = (uint32_t)(M * N) * 8u;
+      const auto ro = piece_rsrc(pp.out + cout, bytes);
+      const bool use_cin = CIN && pp.beta != 0.0 && cin >= 0;
+      const auto rc = piece_rsrc(use_cin ? pp.cin + cin : nullptr, use_cin ? bytes : 0u);
 #pragma unroll
       for (int x = 0; x < MX; ++x)
-        a[p][x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&S.A[p][(16 * x + l % 16) * SLD + kofs]));
 #pragma unroll
-      for (int y = 0; y < MY; ++y)
-        b[p][y] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&S.B[p][(16 * y + l % 16) * SLD + kofs]));
-    }
+        for (int y = 0; y < MY; ++y)
 #pragma unroll
-    for (int x = 0; x < MX; ++x)
-#pragma unroll
-      for (int y = 0; y < MY; ++y) {
-        f32x4 s = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < Terms<NP>::n; ++t)
-          s = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[Terms<NP>::a[t]][x], b[Terms<NP>::b[t]][y], s, 0, 0, 0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[x][y][e] += (double)s[e];
-      }
-  };
-  auto epilogue = [&](const TaskDesc& d) {
-    const int r0 = d.tr * kTile, c0 = d.tc * kTile;
-    const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
-    const ProbPtrs pp = prob(P, d.pid);
-    const bool use_cin = pp.beta != 0.0 && d.cin >= 0;
-    const bool write = !(pp.inplace_skip && d.np == 0);
-#pragma unroll
-    for (int x = 0; x < MX; ++x)
-#pragma unroll
-      for (int y = 0; y < MY; ++y)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = 16 * x + 4 * (l / 16) + e, c = 16 * y + l % 16;
-          if (write && r < mt && c < nt) {
-            const int64_t rel = (int64_t)(r0 + r) * d.N + c0 + c;
-            double v = pp.alpha * acc[x][y][e];
-            if (use_cin) v += pp.beta * pp.cin[d.cin + rel];
-            pp.out[d.cout + rel] = v;
+          for (int e = 0; e < 4; ++e) {
+            const int rr = 16 * x + 4 * (l >> 4) + e, cc = 16 * y + l16;
+            const uint32_t in = (uint32_t)((rr - emt) & (cc - ent)) >> 31;   // rr < emt && cc < ent
+            const uint32_t off = ((uint32_t)((er0 + rr) * N + ec0 + cc) * 8u) | ((in ^ 1u) << 31);
+            double v = pp.alpha * (double)acc[x][y][e];
+            if constexpr (CIN) {
+              if (use_cin)
+                v += pp.beta * __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, (int)off, 0, 0));
+            }
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), ro, (int)off, 0, 0);
           }
-          acc[x][y][e] = 0.0;
-        }
+    }
+#pragma unroll
+    for (int x = 0; x < MX; ++x)
+#pragma unroll
+      for (int y = 0; y < MY; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto compute = [&](const u32x4 (&a)[MX][NP], const u32x4 (&b)[MY][NP]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < Terms<NP>::n; ++t)
+#pragma unroll
+      for (int x = 0; x < MX; ++x)
+#pragma unroll
+        for (int y = 0; y < MY; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[x][Terms<NP>::a[t]]),
+                                                              __builtin_bit_cast(bf16x8, b[y][Terms<NP>::b[t]]),
+                                                              acc[x][y], 0, 0, 0);
   };
 
-  // front = item being gathered, back = item being multiplied (one behind)
-  int fi = t_begin, fc = 0;
-  TaskDesc fd = desc_at(P, fi);
-  int64_t nxw, nyw;
-  load_recs(fi, nxw, nyw);
-  int fn = publish_recs(nxw, nyw);
-  int nch0 = 0, nch1 = 0;
-  auto set_nch = [&](int t, int v) { if (t & 1) nch1 = v; else nch0 = v; };
-  set_nch(fi, fn);
-  if (fi + 1 < t_end) load_recs(fi + 1, nxw, nyw);
-  int tb = 0;
-  __syncthreads();
-  build_tab(tb, 0, fd);
-  __syncthreads();
-  gather(tb, fd);
-
-  int bi = fi, bc = 0;
-  TaskDesc bd = fd;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    R[d] = load_rec();
+    padvance();
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue(A[d], B[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d], tcin[d]);
   while (true) {
-    __syncthreads();
-    stage();
-    bool more = true;
-    if (fc + 1 < fn) {
-      ++fc;
-    } else if (fi + 1 < t_end) {
-      ++fi;
-      fc = 0;
-      fd = desc_at(P, fi);
-      fn = publish_recs(nxw, nyw);
-      set_nch(fi, fn);
-      if (fi + 1 < t_end) load_recs(fi + 1, nxw, nyw);
-      __syncthreads();
-    } else {
-      more = false;
-    }
-    tb ^= 1;
-    if (more) build_tab(tb, fc, fd);
-    __syncthreads();
-    if (more) gather(tb, fd);
-    mma();
-    if (bc + 1 == ((bi & 1) ? nch1 : nch0)) {
-      if (bd.flags & kTaskLast) epilogue(bd);
-      if (!more) break;
-      ++bi;
-      bc = 0;
-      bd = desc_at(P, bi);
-    } else {
-      ++bc;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (!(tflag[d] & 1)) return;
+      compute(A[d], B[d]);
+      if (tflag[d] & 2) epilogue(tpid[d], tmn[d], ttile[d], tcout[d], tcin[d]);
+      issue(A[d], B[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d], tcin[d]);
     }
   }
 }
@@ -287,39 +332,73 @@ struct SplitWaves {
 __host__ __device__ constexpr int split_mx(int c) { return (c / 4 + 2) / 2; }
 __host__ __device__ constexpr int split_my(int c) { return (c % 4 + 2) / 2; }
 
+constexpr int kSplitDepth = 2;
+template <int NP>
+struct SplitBudget {
+  static constexpr int waves = NP == 2 ? 3 : 2;   // resident wavefronts per SIMD
+};
+
 }  // namespace
 
-// Persistent kernel: wavefronts [w[c], w[c+1]) serve class c, each XCD a
-// contiguous eighth of the class's work items.
-template <int NP>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSplitWaves)))
+// Persistent kernel: wavefronts [w[c], w[c+1]) serve class c; local
+// wavefront w runs on XCD w % 8, each XCD owns a contiguous eighth of the
+// class's tiles and its wavefronts take them cyclically.
+template <int NP, bool CIN, bool BATCH>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SplitBudget<NP>::waves)))
 k_numeric_split(NumParams P, SplitWaves W) {
-  __shared__ SplitStage<NP> S;
   const int b = blockIdx.x;
   int c = 0;
   while (c < kClasses - 1 && b >= W.w[c + 1]) ++c;
   const int n = W.w[c + 1] - W.w[c];
   const int w = b - W.w[c];
-  const int L = (w % kXcd) * (n / kXcd) + w / kXcd;
-  const int64_t d0 = P.seg ? P.seg[P.cls_tile[c]] : P.cls_tile[c];
-  const int64_t d1 = P.seg ? P.seg[P.cls_tile[c + 1]] : P.cls_tile[c + 1];
-  const int t_begin = slice_start(P.desc, d0, d1, L, n), t_end = slice_start(P.desc, d0, d1, L + 1, n);
-  if (t_begin >= t_end) return;
+  const int x = w % kXcd, r = w / kXcd;
+  const int64_t d0 = P.cls_tile[c], d1 = P.cls_tile[c + 1];
+  const int e0 = (int)(d0 + x * (d1 - d0) / kXcd), e1 = (int)(d0 + (x + 1) * (d1 - d0) / kXcd);
+  if (e0 + r >= e1) return;
   switch (split_mx(c) * 2 + split_my(c)) {
-    case 3: run_split<1, 1, NP>(P, S, t_begin, t_end); break;
-    case 4: run_split<1, 2, NP>(P, S, t_begin, t_end); break;
-    case 5: run_split<2, 1, NP>(P, S, t_begin, t_end); break;
-    default: run_split<2, 2, NP>(P, S, t_begin, t_end); break;
+    case 3: run_split_steps<1, 1, NP, CIN, BATCH, kSplitDepth>(P, e0, e1, r, n / kXcd); break;
+    case 4: run_split_steps<1, 2, NP, CIN, BATCH, kSplitDepth>(P, e0, e1, r, n / kXcd); break;
+    case 5: run_split_steps<2, 1, NP, CIN, BATCH, kSplitDepth>(P, e0, e1, r, n / kXcd); break;
+    default: run_split_steps<2, 2, NP, CIN, BATCH, kSplitDepth>(P, e0, e1, r, n / kXcd); break;
   }
+}
+
+hipError_t launch_split_rows(hipStream_t s, int npieces, const double* x, int64_t n, int64_t stride, uint16_t* out) {
+  if (stride <= 0) return hipSuccess;
+  if (stride % 4 != 0 || stride < n) return hipErrorInvalidValue;
+  const int64_t q = stride / 4;
+  const dim3 g((unsigned)((q + 255) / 256)), blk(256);
+  if (npieces == 2) hipLaunchKernelGGL((k_split_rows<2>), g, blk, 0, s, x, n, stride, out);
+  else hipLaunchKernelGGL((k_split_rows<3>), g, blk, 0, s, x, n, stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_cols(hipStream_t s, int npieces, const double* y, int64_t nblk, const int32_t* row,
+                             const int32_t* col, const int32_t* blk, const int64_t* off, const int32_t* rs,
+                             const int32_t* cs, int64_t n, int64_t stride, uint16_t* out) {
+  if (stride < n) return hipErrorInvalidValue;
+  if (nblk > 0) {
+    const int64_t groups = std::min<int64_t>((nblk + 3) / 4, 65536);
+    if (npieces == 2)
+      hipLaunchKernelGGL((k_split_cols<2>), dim3((unsigned)groups), dim3(256), 0, s, y, nblk, row, col, blk, off, rs,
+                         cs, stride, out);
+    else
+      hipLaunchKernelGGL((k_split_cols<3>), dim3((unsigned)groups), dim3(256), 0, s, y, nblk, row, col, blk, off, rs,
+                         cs, stride, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t t = (int64_t)npieces * (stride - n);
+  if (t > 0) hipLaunchKernelGGL(k_split_tail, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, npieces, n, stride, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p) {
   if (p.cls_tile[kClasses] == 0) return hipSuccess;
-  if (!p.desc || p.ncu <= 0 || (npieces != 2 && npieces != 3)) return hipErrorInvalidValue;
+  if (!p.desc || !(p.steps || p.ptab) || p.ncu <= 0 || (npieces != 2 && npieces != 3)) return hipErrorInvalidValue;
   if (p.mx != kRowMajor || p.my != kRowMajor || p.mo != kRowMajor) return hipErrorInvalidValue;
-  const int stage = npieces == 2 ? (int)sizeof(SplitStage<2>) : (int)sizeof(SplitStage<3>);
-  const int resident = p.ncu * std::min(4 * kSplitWaves, (160 * 1024) / stage);
-  // wavefronts per class in proportion to work items x padded area, multiples of 8
+  const int resident = p.ncu * 4 * (npieces == 2 ? SplitBudget<2>::waves : SplitBudget<3>::waves);
+  // wavefronts per class in proportion to tiles x padded area, multiples of 8
   SplitWaves cw;
   double wsum = 0.0;
   for (int c = 0; c < kClasses; ++c) wsum += double(p.cls_tile[c + 1] - p.cls_tile[c]) * split_mx(c) * split_my(c);
@@ -334,8 +413,19 @@ hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p) 
     }
     cw.w[c + 1] = (int32_t)(cw.w[c] + w);
   }
-  if (npieces == 2) hipLaunchKernelGGL((k_numeric_split<2>), dim3(cw.w[kClasses]), dim3(64), 0, s, p, cw);
-  else hipLaunchKernelGGL((k_numeric_split<3>), dim3(cw.w[kClasses]), dim3(64), 0, s, p, cw);
+  const bool batch = p.ptab != nullptr;
+  const bool cin = batch ? p.has_cin != 0 : (p.beta != 0.0 && p.cin != nullptr);
+  const dim3 g(cw.w[kClasses]), blk(64);
+#define BSM_SPLIT_LAUNCH(NP_, CIN_, BATCH_) \
+  hipLaunchKernelGGL((k_numeric_split<NP_, CIN_, BATCH_>), g, blk, 0, s, p, cw)
+  if (npieces == 2) {
+    if (batch) { if (cin) BSM_SPLIT_LAUNCH(2, true, true); else BSM_SPLIT_LAUNCH(2, false, true); }
+    else { if (cin) BSM_SPLIT_LAUNCH(2, true, false); else BSM_SPLIT_LAUNCH(2, false, false); }
+  } else {
+    if (batch) { if (cin) BSM_SPLIT_LAUNCH(3, true, true); else BSM_SPLIT_LAUNCH(3, false, true); }
+    else { if (cin) BSM_SPLIT_LAUNCH(3, true, false); else BSM_SPLIT_LAUNCH(3, false, false); }
+  }
+#undef BSM_SPLIT_LAUNCH
   return hipGetLastError();
 }
 

@@ -8,6 +8,9 @@
 // with (r0, c0) the tile's origin in its output block and kv = min(16, K - k0)
 // the step's valid k.  A tile without products has one step with kv = 0 (its
 // output is beta * C_in).  One work item per tile: pbeg / np give its steps.
+// Split-precision plans pair the steps of a tile (one bfloat16 instruction
+// takes two): their step lists are padded to even length with empty steps
+// (all-zero records, kv = 0).
 #include "bsm_internal.h"
 
 namespace bsm {
@@ -106,13 +109,13 @@ __global__ void k_product_chunks(int64_t nprod, const int64_t* __restrict__ px, 
 __global__ void k_tile_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ pptr,
                              const int64_t* __restrict__ chs, const int32_t* __restrict__ c_row,
                              const int32_t* __restrict__ c_col, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, int64_t* __restrict__ nsteps,
+                             const int32_t* __restrict__ cs, int split, int64_t* __restrict__ nsteps,
                              int32_t* __restrict__ blk2tile) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
   const int t = tiles[w].x;
   const int64_t n = chs[pptr[t + 1]] - chs[pptr[t]];
-  nsteps[w] = n > 0 ? n : 1;
+  nsteps[w] = split ? (n > 0 ? (n + 1) & ~int64_t(1) : 2) : (n > 0 ? n : 1);
   const bool single = rs[c_row[t]] <= kTile && cs[c_col[t]] <= kTile;
   if (single) blk2tile[t] = w;
 }
@@ -124,8 +127,8 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
                              const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
                              const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
                              const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, int split, uint64_t* __restrict__ steps,
-                             TaskDesc* __restrict__ desc) {
+                             const int32_t* __restrict__ cs, const int64_t* __restrict__ chs, int split,
+                             uint64_t* __restrict__ steps, TaskDesc* __restrict__ desc) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
   const int t = tiles[w].x;
@@ -150,11 +153,13 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
   d.cls = (uint16_t)tile_class(mt, nt);
   d.pid = 0;
   desc[w] = d;
-  if (p0 == p1) {
-    steps[2 * s] = 0;
-    steps[2 * s + 1] = 0;
-    return;
+  // empty steps: the tile's only one(s) without products, else the padding
+  // after its real steps
+  for (int64_t q = p0 == p1 ? s : s + (chs[p1] - chs[p0]); q < s + d.np; ++q) {
+    steps[2 * q] = 0;
+    steps[2 * q + 1] = 0;
   }
+  if (p0 == p1) return;
   if (M <= kTile && N <= kTile) return;  // written per product
   for (int64_t p = p0; p < p1; ++p) {
     const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
@@ -204,7 +209,7 @@ hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px
 
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
                              const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
-                             const int32_t* cs, int64_t* nsteps, int32_t* blk2tile) {
+                             const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile) {
   if (nblk > 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, blk2tile, nblk, -1);
     const hipError_t e = hipGetLastError();
@@ -212,17 +217,18 @@ hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const 
   }
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, pptr, chs, c_row,
-                     c_col, rs, cs, nsteps, blk2tile);
+                     c_col, rs, cs, (int)split, nsteps, blk2tile);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, bool split, uint64_t* steps, TaskDesc* desc) {
+                             const int32_t* rs, const int32_t* cs, const int64_t* chs, bool split, uint64_t* steps,
+                             TaskDesc* desc) {
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, (int)split, steps, desc);
+                     c_col, c_off, cin_off, pptr, px, py, rs, cs, chs, (int)split, steps, desc);
   return hipGetLastError();
 }
 
