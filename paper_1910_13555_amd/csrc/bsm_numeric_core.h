@@ -60,12 +60,27 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off
 
 constexpr int KS = 16;   // k per pipeline step
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f64x2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+
+// Row-major path: the k (inside a step of 16) that instruction k-step ks
+// takes from lanes of k index lk.  The sum over k is order-free, so the
+// assignment is chosen for the loads: a lane's A values of k-steps (0, 1)
+// and (2, 3) are adjacent pairs (one 16-byte load each), and k-steps 0-1
+// still cover k < 8, so steps with at most 8 valid k skip k-steps 2-3.
+__host__ __device__ constexpr int step_k(int ks, int lk) { return 8 * (ks >> 1) + 2 * lk + (ks & 1); }
+
 // Kernels: (variant, tile size) combinations, each with its own pipeline
 // depth and register budget (resident wavefronts per SIMD).
 constexpr int kKernels = kNumericKernels;
 constexpr int kKernVariant[kKernels] = {0, 0, 0, 1, 1};
 constexpr int kKernDepth[kKernels] = {2, 2, 2, 4, 2};
 constexpr int kKernWaves[kKernels] = {4, 3, 2, 4, 3};
+// with C_in read ahead with the operands (more registers per wavefront)
+constexpr int kKernWavesCin[kKernels] = {4, 2, 2, 3, 2};
+__host__ __device__ constexpr int kern_waves(int kid, bool cin) { return cin ? kKernWavesCin[kid] : kKernWaves[kid]; }
 constexpr int kStepDepth[kKernels] = {2, 2, 2, 4, 2};   // pipeline depth of the row-major path
 
 // Kernel of class c under variant v: tiles up to 16 x 16, with 24, with 32
@@ -343,13 +358,16 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
 
 #pragma unroll
   for (int d = 0; d < D; ++d) issue(A[d], B[d], Cb[d], titem[d], tflag[d]);
-  // steady state; the first empty buffer ends the wavefront's work (leaving
-  // straight out of the loop keeps every path through it issuing the same
-  // loads, so the compiler can count them exactly)
+  // steady state (every path through the loop issues the same loads, so the
+  // compiler can count them exactly).  One exit, at the top: a wavefront's buffers go dead in issue order, so
+  // buffer 0 dead means all are; a dead buffer after the last live one holds
+  // zeros and adds nothing.  (An exit between the buffers would join the loop
+  // latch, and the memory-counter wait at the top would then drain the loads
+  // of every buffer instead of only buffer 0's.)
   while (true) {
+    if (!(tflag[0] & 1)) return;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      if (!(tflag[d] & 1)) return;
       compute(A[d], B[d], tflag[d] >> 2);
       if (tflag[d] & 2) epilogue(desc_at(P, titem[d]), Cb[d]);
       issue(A[d], B[d], Cb[d], titem[d], tflag[d]);
@@ -432,7 +450,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
       const int c = TI * y + lcB;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
-        offB[y][ks] = c < nt ? (uint32_t)((4 * ks + lk) * (int)d.N + c) * 8u : kOob;
+        offB[y][ks] = c < nt ? (uint32_t)(step_k(ks, lk) * (int)d.N + c) * 8u : kOob;
     }
 #pragma unroll
     for (int x = 0; x < NI; ++x) {
@@ -464,11 +482,18 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     const auto ra = make_rsrc((const double*)((const char*)X + (w0 & kMask48)), 0x7ffffff8u);
     const auto rb = make_rsrc((const double*)((const char*)Y + (w1 & kMask48)),
                               kv > 0 ? (uint32_t)(kv * N8 - c08) : 0u);
+    // A: the lane's k pairs (2 lk, 2 lk + 1) and (8 + 2 lk, 9 + 2 lk), one
+    // 16-byte load each; a value past the step's valid k reads zero
+    const int c0v = kv - 2 * lk, c1v = kv - 8 - 2 * lk;   // valid values of each pair (if < 2)
 #pragma unroll
     for (int x = 0; x < NI; ++x) {
-      const uint32_t base = rowA[x] >= 0 ? (uint32_t)(rowA[x] * K8 + lk * 8) : kOob;
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) a[x][ks] = buf_load(ra, 4 * ks + lk < kv ? base + 32u * ks : kOob);
+      const uint32_t base = (uint32_t)(rowA[x] * K8 + lk * 16);
+      const f64x2 p0 = buf_load2(ra, rowA[x] >= 0 && c0v > 0 ? base : kOob);
+      const f64x2 p1 = buf_load2(ra, rowA[x] >= 0 && c1v > 0 ? base + 64u : kOob);
+      a[x][0] = p0[0];
+      a[x][1] = c0v > 1 ? p0[1] : 0.0;
+      a[x][2] = p1[0];
+      a[x][3] = c1v > 1 ? p1[1] : 0.0;
     }
 #pragma unroll
     for (int y = 0; y < NJ; ++y)
@@ -578,10 +603,15 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d]);
+  // One exit, at the top: a wavefront's buffers go dead in issue order, so
+  // buffer 0 dead means all are; a dead buffer after the last live one holds
+  // zeros and adds nothing.  (An exit between the buffers would join the loop
+  // latch, and the memory-counter wait at the top would then drain the loads
+  // of every buffer instead of only buffer 0's.)
   while (true) {
+    if (!(tflag[0] & 1)) return;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      if (!(tflag[d] & 1)) return;
       compute(A[d], B[d], (tflag[d] & 4) != 0);
       if (tflag[d] & 2) epilogue(Cb[d], tpid[d], tmn[d], ttile[d], tcout[d]);
       issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d]);
@@ -617,7 +647,8 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
 #define BSM_SHAPE(NI_, NJ_)                                                              \
   case NI_ * 8 + NJ_:                                                                    \
     if constexpr (V == 0 ? kernel_of((NI_ - 1) * 4 + NJ_ - 1, 0) == KID                  \
-                         : kernel_of((2 * NI_ - 1) * 4 + 2 * NJ_ - 1, 1) == KID)         \
+                         : NI_ <= 2 && NJ_ <= 2 &&                                       \
+                               kernel_of((2 * NI_ - 1) * 4 + 2 * NJ_ - 1, 1) == KID)     \
       if constexpr (GEN) run_tiles<V, NI_, NJ_, GEN, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd); \
       else run_steps<V, NI_, NJ_, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd);                 \
     break;
@@ -635,7 +666,7 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
 // row-major path, so that the epilogue never waits on memory).  BATCH: the
 // buffers and scalars come from the per-problem table.
 template <bool GEN, bool CIN, bool BATCH, int KID>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kKernWaves[KID])))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kern_waves(KID, CIN && !GEN))))
 k_numeric(NumParams P, ClassWaves W) {
   numeric_body<GEN, CIN, BATCH, KID>(P, W.w);
 }
@@ -676,7 +707,7 @@ hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
   ClassWaves cw[kKernels];
   int nfam = 0;
   for (int kid = 0; kid < kKernels; ++kid) {
-    cw[kid] = class_waves(p, kid, p.ncu * 4 * kKernWaves[kid]);
+    cw[kid] = class_waves(p, kid, p.ncu * 4 * kern_waves(kid, CIN && !GEN));
     nfam += cw[kid].w[kClasses] > 0;
   }
   const bool conc = p.side && nfam > 1;

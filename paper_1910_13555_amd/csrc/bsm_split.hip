@@ -313,10 +313,15 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) issue(A[d], B[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d], tcin[d]);
+  // One exit, at the top: a wavefront's buffers go dead in issue order, so
+  // buffer 0 dead means all are; a dead buffer after the last live one holds
+  // zeros and adds nothing.  (An exit between the buffers would join the loop
+  // latch, and the memory-counter wait at the top would then drain the loads
+  // of every buffer instead of only buffer 0's.)
   while (true) {
+    if (!(tflag[0] & 1)) return;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      if (!(tflag[d] & 1)) return;
       compute(A[d], B[d]);
       if (tflag[d] & 2) epilogue(tpid[d], tmn[d], ttile[d], tcout[d], tcin[d]);
       issue(A[d], B[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d], tcin[d]);
