@@ -381,11 +381,11 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
 // record (A: the block from A(r0, k0) on, reads guarded by the k test; B: the
 // block from B(k0, c0) on, sized so that rows past the step's valid k read
 // zero), one offset select per A operand, none for B (per-tile lane offsets),
-// and the matrix-core instructions.  A step's record is loaded with the
-// operands of the step D earlier, through the same in-order vector memory
-// counter, so its wait never holds back the pipeline; tile descriptors come
-// through scalar loads one tile ahead, and the fields the epilogue needs
-// travel with the step.
+// and the matrix-core instructions.  A step's record is a scalar load
+// issued with the operands of the step D earlier (scalar loads keep the
+// records off the vector memory path, whose address unit bounds these
+// kernels); tile descriptors come through scalar loads one tile ahead, and
+// the fields the epilogue needs travel with the step.
 template <int V, int NI, int NJ, bool CIN, bool BATCH, int D>
 __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, int r, int stride) {
   const int l = threadIdx.x;
@@ -410,7 +410,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   if (pt + stride < e1) pdn = desc_at(P, pt + stride);
   auto load_rec = [&]() __attribute__((always_inline)) {
     const uint64_t* q = plive ? psteps + 2 * (int64_t)ps : first_rec;
-    return *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(gptr(q));
+    return *cptr(reinterpret_cast<const u32x4*>(q));
   };
   auto padvance = [&]() __attribute__((always_inline)) {
     if (!plive) return;
@@ -472,8 +472,8 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   auto issue = [&](double (&a)[NI][4], double (&b)[NJ][4], double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1],
                    u32x4& rec, int& flag, int& pid, int& mn, int& tile, int64_t& cout) __attribute__((always_inline)) {
     const bool live = it < e1;
-    const uint64_t w0 = ((uint64_t)__builtin_amdgcn_readfirstlane(rec[1]) << 32) | __builtin_amdgcn_readfirstlane(rec[0]);
-    const uint64_t w1 = ((uint64_t)__builtin_amdgcn_readfirstlane(rec[3]) << 32) | __builtin_amdgcn_readfirstlane(rec[2]);
+    const uint64_t w0 = ((uint64_t)rec[1] << 32) | rec[0];
+    const uint64_t w1 = ((uint64_t)rec[3] << 32) | rec[2];
     // the record for this buffer's next step, D steps ahead
     rec = load_rec();
     padvance();
