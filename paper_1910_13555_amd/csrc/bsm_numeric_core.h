@@ -434,6 +434,16 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   const double* X = nullptr;
   const double* Y = nullptr;
   int mt = 0, N8 = 0, c08 = 0;
+  // Column pairs: instruction tiles 2p and 2p + 1 hold the even and the odd
+  // columns of a span of 2 TI columns, so a lane's B values of both tiles are
+  // adjacent (one 16-byte load; a pair's second value past the step's last
+  // valid row is cut by the per-dword range check, one past the tile feeds
+  // only a column that is never stored).  16x16x4: tiles 32 wide; 4x4x4:
+  // every two 8-column tiles.
+  constexpr int NPAIR = V == 1 ? (NJ == 2 ? 1 : 0) : NJ / 2;
+  auto bcol = [&](int y) __attribute__((always_inline)) {   // tile column of this lane in instruction tile y
+    return y < 2 * NPAIR ? 2 * TI * (y >> 1) + 2 * lcB + (y & 1) : TI * y + lcB;
+  };
   uint32_t offB[NJ][4];
   int rowA[NI];
   auto enter = [&](const TaskDesc& d) __attribute__((always_inline)) {
@@ -447,7 +457,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     c08 = c0 * 8;
 #pragma unroll
     for (int y = 0; y < NJ; ++y) {
-      const int c = TI * y + lcB;
+      const int c = bcol(y);   // a pair's load: from its even tile's column
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         offB[y][ks] = c < nt ? (uint32_t)(step_k(ks, lk) * (int)d.N + c) * 8u : kOob;
@@ -496,9 +506,19 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
       a[x][3] = c1v > 1 ? p1[1] : 0.0;
     }
 #pragma unroll
-    for (int y = 0; y < NJ; ++y)
+    for (int y = 0; y < NJ; ++y) {
+      if (y < 2 * NPAIR && (y & 1)) continue;   // loaded with its pair
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) b[y][ks] = buf_load(rb, offB[y][ks]);
+      for (int ks = 0; ks < 4; ++ks) {
+        if (y < 2 * NPAIR) {
+          const f64x2 v = buf_load2(rb, offB[y][ks]);
+          b[y][ks] = v[0];
+          b[y + 1][ks] = v[1];
+        } else {
+          b[y][ks] = buf_load(rb, offB[y][ks]);
+        }
+      }
+    }
     const bool last = s + 1 >= se;
     if constexpr (PRE) {
       // the tile's C_in, requested with its last step (every step issues
@@ -515,7 +535,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
 #pragma unroll
           for (int e = 0; e < NE; ++e) {
             const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
-            const int cc = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+            const int cc = bcol(y);
             const uint32_t off = (rr < mt && cc < nt) ? (uint32_t)((r0 + rr) * id.N + c0 + cc) * 8u : kOob;
             cb[x][y][e] = buf_load(rc, off);
           }
@@ -560,7 +580,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
 #pragma unroll
           for (int e = 0; e < NE; ++e) {
             const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
-            const int cc = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+            const int cc = bcol(y);
             double av;
             if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
             // branch-free: lanes outside the tile get an offset past the block
