@@ -555,9 +555,12 @@ bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals, c
     if (A->ctx != ctx) fail(BSM_E_INVALID, "pattern of another context");
     if (o.precision != BSM_PREC_FP64 && (o.trans_a || o.trans_b))
       fail(BSM_E_UNSUPPORTED, "split precision needs untransposed operands");
-    if (o.precision != BSM_PREC_FP64 &&
-        (piece_stride(A->nvals) >= (int64_t(1) << 30) || piece_stride(B->nvals) >= (int64_t(1) << 30)))
-      fail(BSM_E_UNSUPPORTED, "split precision: operands of at most 2^30 - 80 values");
+    if (o.precision != BSM_PREC_FP64) {  // each operand's piece arrays together under 2 GB
+      const int64_t lim = (int64_t(1) << 30) / split_pieces(o.precision);
+      if (piece_stride(A->nvals) >= lim || piece_stride(B->nvals) >= lim)
+        fail(BSM_E_UNSUPPORTED, "split precision: operands of at most %lld values",
+             (long long)(lim - 80));
+    }
     set_device(ctx);
     auto pl = std::make_unique<bsm_plan_s>();
     pl->ctx = ctx;

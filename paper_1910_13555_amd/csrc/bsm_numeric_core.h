@@ -77,10 +77,14 @@ __host__ __device__ constexpr int step_k(int ks, int lk) { return 8 * (ks >> 1) 
 constexpr int kKernels = kNumericKernels;
 constexpr int kKernVariant[kKernels] = {0, 0, 0, 1, 1};
 constexpr int kKernDepth[kKernels] = {2, 2, 2, 4, 2};
-constexpr int kKernWaves[kKernels] = {4, 3, 2, 4, 3};
-// with C_in read ahead with the operands (more registers per wavefront)
+constexpr int kKernWaves[kKernels] = {5, 3, 2, 5, 4};
+// row-major path with C_in read ahead with the operands (more registers per
+// wavefront), and the generic-layout path
 constexpr int kKernWavesCin[kKernels] = {4, 2, 2, 3, 2};
-__host__ __device__ constexpr int kern_waves(int kid, bool cin) { return cin ? kKernWavesCin[kid] : kKernWaves[kid]; }
+constexpr int kKernWavesGen[kKernels] = {4, 3, 2, 4, 3};
+__host__ __device__ constexpr int kern_waves(int kid, bool gen, bool cin) {
+  return gen ? kKernWavesGen[kid] : cin ? kKernWavesCin[kid] : kKernWaves[kid];
+}
 constexpr int kStepDepth[kKernels] = {2, 2, 2, 4, 2};   // pipeline depth of the row-major path
 
 // Kernel of class c under variant v: tiles up to 16 x 16, with 24, with 32
@@ -686,7 +690,7 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
 // row-major path, so that the epilogue never waits on memory).  BATCH: the
 // buffers and scalars come from the per-problem table.
 template <bool GEN, bool CIN, bool BATCH, int KID>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kern_waves(KID, CIN && !GEN))))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kern_waves(KID, GEN, CIN))))
 k_numeric(NumParams P, ClassWaves W) {
   numeric_body<GEN, CIN, BATCH, KID>(P, W.w);
 }
@@ -727,7 +731,7 @@ hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
   ClassWaves cw[kKernels];
   int nfam = 0;
   for (int kid = 0; kid < kKernels; ++kid) {
-    cw[kid] = class_waves(p, kid, p.ncu * 4 * kern_waves(kid, CIN && !GEN));
+    cw[kid] = class_waves(p, kid, p.ncu * 4 * kern_waves(kid, GEN, CIN));
     nfam += cw[kid].w[kClasses] > 0;
   }
   const bool conc = p.side && nfam > 1;

@@ -32,8 +32,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 
-constexpr uint32_t kOobS = 0x80000000u;   // an offset past every piece array (< 2 GB each)
+constexpr uint32_t kOobS = 0x80000000u;   // an offset past every operand's piece arrays (< 2 GB together)
 
 // Round to nearest even, float32 -> bfloat16 bits (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
@@ -134,8 +135,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t piece_rsrc(const void* base, u
 }
 
 // Loop over this wavefront's tiles of one class, MX x MY instructions of
-// 16 x 16 per tile, D pairs of steps in flight.  Records: lane l reads the
-// record of step 2 j + l / 32 of its pair j.
+// 16 x 16 per tile, D pairs of steps in flight.  Lane l takes the record of
+// step 2 j + l / 32 of its pair j.
 template <int MX, int MY, int NP, bool CIN, bool BATCH, int D>
 __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int e1, int r, int stride) {
   const int l = threadIdx.x;
@@ -153,9 +154,10 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
   const uint64_t* const first_rec = psteps + 2 * (int64_t)ps;
   bool plive = true;
   if (pt + stride < e1) pdn = desc_at(P, pt + stride);
+  // both records of a pair in one scalar load (kept off the vector memory path)
   auto load_rec = [&]() __attribute__((always_inline)) {
-    const uint64_t* q = plive ? psteps + 2 * (int64_t)(ps + sp) : first_rec;
-    return *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(gptr(q));
+    const uint64_t* q = plive ? psteps + 2 * (int64_t)ps : first_rec;
+    return *cptr(reinterpret_cast<const u32x8*>(q));
   };
   auto padvance = [&]() __attribute__((always_inline)) {
     if (!plive) return;
@@ -177,17 +179,17 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
   TaskDesc nd = id;
   if (it + stride < e1) nd = desc_at(P, it + stride);
   int s = (int)id.pbeg, se = s + id.np;
-  __amdgpu_buffer_rsrc_t ra[NP], rb[NP];
+  // one resource per operand over all its piece arrays (together < 2 GB):
+  // piece p of a value at offset + p * piece bytes
+  __amdgpu_buffer_rsrc_t ra, rb;
+  uint32_t xpb = 0, ypb = 0;
   int rowA[MX], colB[MY];
   auto enter = [&](const TaskDesc& d) __attribute__((always_inline)) {
     const ProbPtrs pp = prob<BATCH>(P, d.pid);
-    const char* xa = reinterpret_cast<const char*>(pp.X);
-    const char* yb = reinterpret_cast<const char*>(pp.Y);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      ra[p] = piece_rsrc(xa + (size_t)p * pp.xpb, pp.xpb);
-      rb[p] = piece_rsrc(yb + (size_t)p * pp.ypb, pp.ypb);
-    }
+    xpb = pp.xpb;
+    ypb = pp.ypb;
+    ra = piece_rsrc(pp.X, NP * xpb);
+    rb = piece_rsrc(pp.Y, NP * ypb);
     const int mt = min(kTile, (int)d.M - d.tr * kTile), nt = min(kTile, (int)d.N - d.tc * kTile);
 #pragma unroll
     for (int x = 0; x < MX; ++x) rowA[x] = 16 * x + l16 < mt ? 16 * x + l16 : -1;
@@ -197,15 +199,18 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
   enter(id);
 
   u32x4 A[D][MX][NP], B[D][MY][NP];
-  u32x4 R[D];
+  u32x8 R[D];
   int tflag[D], tpid[D], tmn[D], ttile[D];
   int64_t tcout[D], tcin[D];
 
-  auto issue = [&](u32x4 (&a)[MX][NP], u32x4 (&b)[MY][NP], u32x4& rec, int& flag, int& pid, int& mn, int& tile,
+  auto issue = [&](u32x4 (&a)[MX][NP], u32x4 (&b)[MY][NP], u32x8& rec, int& flag, int& pid, int& mn, int& tile,
                    int64_t& cout, int64_t& cin) __attribute__((always_inline)) {
     const bool live = it < e1;
-    const uint64_t w0 = ((uint64_t)rec[1] << 32) | rec[0];
-    const uint64_t w1 = ((uint64_t)rec[3] << 32) | rec[2];
+    // this lane's record: the pair's first (lanes 0-31) or second
+    const uint32_t w0lo = sp ? rec[4] : rec[0], w0hi = sp ? rec[5] : rec[1];
+    const uint32_t w1lo = sp ? rec[6] : rec[2], w1hi = sp ? rec[7] : rec[3];
+    const uint64_t w0 = ((uint64_t)w0hi << 32) | w0lo;
+    const uint64_t w1 = ((uint64_t)w1hi << 32) | w1lo;
     rec = load_rec();
     padvance();
     const int K2 = (int)(w0 >> 48) * 2;
@@ -222,7 +227,7 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
       const uint32_t o = (rowA[x] >= 0 && cnt > 0) ? ao + (uint32_t)(rowA[x] * K2) : kOobS;
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        u32x4 v = load16(ra[p], o);
+        u32x4 v = load16(ra, o + p * xpb);
         v[0] &= m[0]; v[1] &= m[1]; v[2] &= m[2]; v[3] &= m[3];
         a[x][p] = v;
       }
@@ -232,7 +237,7 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
       const uint32_t o = (colB[y] >= 0 && cnt > 0) ? bo + (uint32_t)(colB[y] * K2) : kOobS;
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        u32x4 v = load16(rb[p], o);
+        u32x4 v = load16(rb, o + p * ypb);
         v[0] &= m[0]; v[1] &= m[1]; v[2] &= m[2]; v[3] &= m[3];
         b[y][p] = v;
       }
