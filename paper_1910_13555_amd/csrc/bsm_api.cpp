@@ -161,6 +161,15 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                max_tiles(ta ? A->h_cs : A->h_rs, tb ? B->h_rs : B->h_cs), pl->seg, pl->desc);
   } else if (pl->ntasks > 0) {
     const bool split = pl->opts.precision != BSM_PREC_FP64;
+    PieceMap pm;
+    if (split) {
+      pm.aoff = A->d_off.p;
+      pm.na = A->nblk;
+      pm.apad = pl->apad.p;
+      pm.boff = B->d_off.p;
+      pm.nb = B->nblk;
+      pm.bpad = pl->bpad.p;
+    }
     // step records (no readback: the symbolic count bounds them, tiles
     // without products add one step each, split plans one padding step per
     // tile at most)
@@ -180,13 +189,38 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
     hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
                                 pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, chs.p,
-                                split, pl->steps.p, pl->sdesc.p),
+                                pm, pl->steps.p, pl->sdesc.p),
               "work items");
     hip_check(launch_product_steps(st, pl->nprod, pl->c_nblk, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
-                                   pl->c_cs, pl->px.p, pl->py.p, split, pl->steps.p),
+                                   pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
               "product steps");
   }
   // temporaries go back to the allocator: later work on this stream is ordered after the fill
+}
+
+// Split precision: offsets of a pattern's stored blocks in the padded piece
+// layout (rows padded to a multiple of 8 values; trans: columns), nblk + 1
+// entries, the last one the padded size.
+std::vector<int64_t> piece_offsets(bsm_pattern P, bool trans) {
+  P->ensure_host();
+  std::vector<int64_t> pad(P->nblk + 1, 0);
+  for (int64_t e = 0; e < P->nblk; ++e) {
+    const int R = P->h_rs[P->h_row[e]], C = P->h_cs[P->h_col[e]];
+    pad[P->stored(e) + 1] = (int64_t)(trans ? C : R) * pad8(trans ? R : C);
+  }
+  for (int64_t s = 0; s < P->nblk; ++s) pad[s + 1] += pad[s];
+  return pad;
+}
+
+void split_operands(bsm_plan pl, int np, const double* x, const double* y, int64_t sx, int64_t sy, uint16_t* xp,
+                    uint16_t* yp, hipStream_t st) {
+  bsm_pattern A = pl->A, B = pl->B;
+  hip_check(launch_split_blocks(st, np, x, A->nblk, A->d_row.p, A->d_col.p, A->h_blk.empty() ? nullptr : A->d_blk.p,
+                                A->d_off.p, pl->apad.p, A->d_rs.p, A->d_cs.p, 0, pl->apad_n, sx, xp),
+            "split A");
+  hip_check(launch_split_blocks(st, np, y, B->nblk, B->d_row.p, B->d_col.p, B->h_blk.empty() ? nullptr : B->d_blk.p,
+                                B->d_off.p, pl->bpad.p, B->d_rs.p, B->d_cs.p, 1, pl->bpad_n, sy, yp),
+            "split B");
 }
 
 void validate_mm(bsm_pattern A, bsm_pattern B, bsm_pattern C, double eps, const bsm_mm_opts& o) {
@@ -256,14 +290,10 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   // allocator after the launch; later work on the stream is ordered after it)
   const int np = split_pieces(pl->opts.precision);
   hipStream_t st = pl->ctx->stream;
-  bsm_pattern A = pl->A, B = pl->B;
-  const int64_t sx = piece_stride(A->nvals), sy = piece_stride(B->nvals);
+  const int64_t sx = piece_stride(pl->apad_n), sy = piece_stride(pl->bpad_n);
   DBuf<uint16_t> xp(pl->ctx, (size_t)np * sx), yp(pl->ctx, (size_t)np * sy);
   if (pl->nprod > 0) {  // else every tile is empty and no operand is read
-    hip_check(launch_split_rows(st, np, x, A->nvals, sx, xp.p), "split A");
-    hip_check(launch_split_cols(st, np, y, B->nblk, B->d_row.p, B->d_col.p, B->h_blk.empty() ? nullptr : B->d_blk.p,
-                                B->d_off.p, B->d_rs.p, B->d_cs.p, B->nvals, sy, yp.p),
-              "split B");
+    split_operands(pl, np, x, y, sx, sy, xp.p, yp.p, st);
   }
   P.X = reinterpret_cast<const double*>(xp.p);
   P.Y = reinterpret_cast<const double*>(yp.p);
@@ -555,10 +585,13 @@ bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals, c
     if (A->ctx != ctx) fail(BSM_E_INVALID, "pattern of another context");
     if (o.precision != BSM_PREC_FP64 && (o.trans_a || o.trans_b))
       fail(BSM_E_UNSUPPORTED, "split precision needs untransposed operands");
+    std::vector<int64_t> apad, bpad;
     if (o.precision != BSM_PREC_FP64) {  // each operand's piece arrays together under 2 GB
+      apad = piece_offsets(A, false);
+      bpad = piece_offsets(B, true);
       const int64_t lim = (int64_t(1) << 30) / split_pieces(o.precision);
-      if (piece_stride(A->nvals) >= lim || piece_stride(B->nvals) >= lim)
-        fail(BSM_E_UNSUPPORTED, "split precision: operands of at most %lld values",
+      if (piece_stride(apad.back()) >= lim || piece_stride(bpad.back()) >= lim)
+        fail(BSM_E_UNSUPPORTED, "split precision: operands of at most %lld values (rows padded to 8)",
              (long long)(lim - 80));
     }
     set_device(ctx);
@@ -568,6 +601,12 @@ bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals, c
     pl->B = B;
     pl->Cin = C_in;
     pl->opts = o;
+    if (!apad.empty()) {
+      pl->apad = make_dev(ctx, apad);
+      pl->bpad = make_dev(ctx, bpad);
+      pl->apad_n = apad.back();
+      pl->bpad_n = bpad.back();
+    }
     pl->eps = filter_eps;
     pl->mx = o.trans_a ? kColMajor : kRowMajor;
     pl->my = o.trans_b ? kColMajor : kRowMajor;

@@ -116,8 +116,8 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
     const int np = split_pieces(b->precision);
     int64_t at = 0;
     for (int32_t p = 0; p < n; ++p) {
-      b->sx.push_back(piece_stride(b->plans[p]->A->nvals));
-      b->sy.push_back(piece_stride(b->plans[p]->B->nvals));
+      b->sx.push_back(piece_stride(b->plans[p]->apad_n));
+      b->sy.push_back(piece_stride(b->plans[p]->bpad_n));
       b->xoff.push_back(at);
       at += np * b->sx.back();
       b->yoff.push_back(at);
@@ -195,13 +195,14 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
     for (int32_t p = 0; p < n; ++p) {
       bsm_plan pl = b->plans[p];
       if (pl->nprod == 0) continue;
-      uint16_t* xp = b->pieces.p + b->xoff[p];
-      uint16_t* yp = b->pieces.p + b->yoff[p];
-      bsm_pattern B = pl->B;
-      hipError_t e = launch_split_rows(st, np, a[p], pl->A->nvals, b->sx[p], xp);
+      bsm_pattern A = pl->A, B = pl->B;
+      hipError_t e = launch_split_blocks(st, np, a[p], A->nblk, A->d_row.p, A->d_col.p,
+                                         A->h_blk.empty() ? nullptr : A->d_blk.p, A->d_off.p, pl->apad.p, A->d_rs.p,
+                                         A->d_cs.p, 0, pl->apad_n, b->sx[p], b->pieces.p + b->xoff[p]);
       if (e == hipSuccess)
-        e = launch_split_cols(st, np, bv[p], B->nblk, B->d_row.p, B->d_col.p, B->h_blk.empty() ? nullptr : B->d_blk.p,
-                              B->d_off.p, B->d_rs.p, B->d_cs.p, B->nvals, b->sy[p], yp);
+        e = launch_split_blocks(st, np, bv[p], B->nblk, B->d_row.p, B->d_col.p,
+                                B->h_blk.empty() ? nullptr : B->d_blk.p, B->d_off.p, pl->bpad.p, B->d_rs.p,
+                                B->d_cs.p, 1, pl->bpad_n, b->sy[p], b->pieces.p + b->yoff[p]);
       if (e != hipSuccess) return e;
     }
     return launch_numeric_split(st, np, P);

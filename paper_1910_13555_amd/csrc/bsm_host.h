@@ -430,6 +430,10 @@ struct bsm_plan_s {
   DBuf<uint64_t> steps;
   DBuf<TaskDesc> sdesc;
   int64_t nsteps = 0;
+  // split precision: stored-block offsets of A and B in the padded piece
+  // layout (nblk + 1 each; the last entry is the padded size)
+  DBuf<int64_t> apad, bpad;
+  int64_t apad_n = 0, bpad_n = 0;
   bool step_path() const {  // row-major operands and output (FP64 or split precision)
     return mx == bsm::kRowMajor && my == bsm::kRowMajor && mo == bsm::kRowMajor && !rowq.p;
   }

@@ -171,18 +171,29 @@ hipError_t launch_fill_steps(hipStream_t s, int32_t ntiles, const int2* tiles, c
 // (and the single-tile block map); work items, empty-tile steps and steps of
 // multi-tile blocks; steps of single-tile blocks per product.
 hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, int64_t* chunks);
+// Split precision: the padded piece layout of both operands -- element
+// offsets of their stored blocks (ascending, n + 1 entries) and the offsets
+// of the same blocks in the piece arrays.  Null apad: a float64 plan.
+struct PieceMap {
+  const int64_t* aoff = nullptr;
+  const int64_t* apad = nullptr;
+  int64_t na = 0;
+  const int64_t* boff = nullptr;
+  const int64_t* bpad = nullptr;
+  int64_t nb = 0;
+};
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
                              const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
                              const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile);
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, const int64_t* chs, bool split, uint64_t* steps,
-                             TaskDesc* desc);
+                             const int32_t* rs, const int32_t* cs, const int64_t* chs, const PieceMap& pm,
+                             uint64_t* steps, TaskDesc* desc);
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
                                 const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
                                 const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
-                                bool split, uint64_t* steps);
+                                const PieceMap& pm, uint64_t* steps);
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);
@@ -194,17 +205,20 @@ bool set_variants(const int32_t* in16);
 // operands only), npieces bfloat16 pieces per value (2: bf16x3, 3: bf16x6).
 // X / Y of p are the piece arrays (p.xpb / p.ypb bytes per piece).
 hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p);
-// Piece arrays: piece p of n values at out + p * stride, elements [n, stride)
-// zero.  Rows: the values' own order (stride a multiple of 4).  Cols: every
-// block of a pattern (entries row/col, stored index blk or identity, stored
-// offsets off, block sizes rs/cs) transposed.
-hipError_t launch_split_rows(hipStream_t s, int npieces, const double* x, int64_t n, int64_t stride, uint16_t* out);
-hipError_t launch_split_cols(hipStream_t s, int npieces, const double* y, int64_t nblk, const int32_t* row,
-                             const int32_t* col, const int32_t* blk, const int64_t* off, const int32_t* rs,
-                             const int32_t* cs, int64_t n, int64_t stride, uint16_t* out);
+// Piece arrays of an operand in the padded layout: the blocks of a pattern
+// (entries row/col, stored index blk or identity, stored offsets off, block
+// sizes rs/cs), block s at pad[s]; untransposed (trans = 0): its rows, each
+// padded with zeros to a multiple of 8 values; trans = 1: its columns, each
+// padded likewise.  Piece p at out + p * stride; elements [n, stride) zero
+// (n = pad[nblk]).
+hipError_t launch_split_blocks(hipStream_t s, int npieces, const double* v, int64_t nblk, const int32_t* row,
+                               const int32_t* col, const int32_t* blk, const int64_t* off, const int64_t* pad,
+                               const int32_t* rs, const int32_t* cs, int trans, int64_t n, int64_t stride,
+                               uint16_t* out);
 // Elements per piece array of n values (zero tail of at least 16: a lane's
 // 16-byte load never straddles the array's end).
 inline int64_t piece_stride(int64_t n) { return ((n + 16 + 63) / 64) * 64; }
+__host__ __device__ inline int pad8(int k) { return (k + 7) & ~7; }
 inline int split_pieces(int precision) { return precision == 2 ? 3 : 2; }
 // Batches: copy one plan's work items (class c at [sbeg[c], sbeg[c+1])) to
 // dbeg[c] of a merged list, tagged with problem pid.

@@ -11,16 +11,17 @@
 // phase stay float64.
 //
 // Two passes per execute:
-//  1. the operands are split once into piece arrays (A: the values' own
-//     element order; B: every block transposed, element (k, c) of a K x N
-//     block at offset + c K + k), so that the 8 consecutive k a lane feeds to
-//     the 16x16x32 instruction are one 16-byte load;
+//  1. the operands are split once into piece arrays in a padded layout (A:
+//     every block row padded with zeros to Kp, K rounded up to 8; B: every
+//     block transposed, each column padded likewise, element (k, c) of a
+//     K x N block at c Kp + k), so that the 8 consecutive k a lane feeds to
+//     the 16x16x32 instruction are one aligned 16-byte load;
 //  2. the persistent kernel walks the step records of the row-major path (one
 //     work item per output tile, a step = one product's k range of 16), two
 //     steps per instruction: lanes 0-31 carry the even step of a pair, lanes
 //     32-63 the odd one (each tile's step list has even length).  Slots past
-//     a step's valid k, rows past the tile and columns past the tile read
-//     zero.
+//     K hold the padding zeros; groups past the step, rows past the tile and
+//     columns past the tile read zero.
 // Row-major operands and output only (no transposition, no tensor layouts).
 #include "bsm_device.h"
 
@@ -58,45 +59,32 @@ __device__ __forceinline__ void split_value(double x, uint32_t (&p)[NP]) {
 
 // ------------------------------------------------------------ piece arrays
 
-// Pieces of n values in their own order, four per thread; piece p at
-// out + p * stride; elements [n, stride) are zero (stride: a multiple of 4).
+// Pieces of the blocks of a pattern in the padded layout; one wavefront per
+// block entry, padded index space in order (coalesced stores).  Block s (a
+// R x C block at off[s]) goes to pad[s]: untransposed, row r at r * pad8(C)
+// holding (r, 0 .. C-1) then zeros; transposed, column c at c * pad8(R)
+// holding (0 .. R-1, c) then zeros.
 template <int NP>
-__global__ void k_split_rows(const double* __restrict__ x, int64_t n, int64_t stride, uint16_t* __restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i0 = 4 * q;
-  if (i0 >= stride) return;
-  uint32_t pc[4][NP];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) split_value<NP>(i0 + j < n ? x[i0 + j] : 0.0, pc[j]);
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    uint2 v;
-    v.x = pc[0][p] | (pc[1][p] << 16);
-    v.y = pc[2][p] | (pc[3][p] << 16);
-    *reinterpret_cast<uint2*>(out + p * stride + i0) = v;
-  }
-}
-
-// Pieces of the blocks of a pattern, each K x N block transposed; one
-// wavefront per block entry.  Elements [n, stride) of each piece are
-// written by k_split_tail.
-template <int NP>
-__global__ void k_split_cols(const double* __restrict__ y, int64_t nblk, const int32_t* __restrict__ row,
-                             const int32_t* __restrict__ col, const int32_t* __restrict__ blk,
-                             const int64_t* __restrict__ off, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, int64_t stride, uint16_t* __restrict__ out) {
+__global__ void k_split_blocks(const double* __restrict__ v, int64_t nblk, const int32_t* __restrict__ row,
+                               const int32_t* __restrict__ col, const int32_t* __restrict__ blk,
+                               const int64_t* __restrict__ off, const int64_t* __restrict__ pad,
+                               const int32_t* __restrict__ rs, const int32_t* __restrict__ cs, int trans,
+                               int64_t stride, uint16_t* __restrict__ out) {
   const int l = threadIdx.x % kWave;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; e < nblk; e += nw) {
-    const int64_t o = off[blk ? blk[e] : e];
-    const int K = rs[row[e]], N = cs[col[e]];
-    const int64_t KN = (int64_t)K * N;
-    for (int64_t idx = l; idx < KN; idx += kWave) {
-      const int64_t k = idx / N, c = idx - k * N;
+    const int64_t sb = blk ? blk[e] : e;
+    const int64_t o = off[sb], po = pad[sb];
+    const int R = rs[row[e]], C = cs[col[e]];
+    const int lines = trans ? C : R, K = trans ? R : C, Kp = pad8(K);
+    const int64_t n = (int64_t)lines * Kp;
+    for (int64_t idx = l; idx < n; idx += kWave) {
+      const int64_t q = idx / Kp, k = idx - q * Kp;
+      const double x = k < K ? v[trans ? o + k * C + q : o + q * C + k] : 0.0;
       uint32_t pc[NP];
-      split_value<NP>(y[o + idx], pc);
+      split_value<NP>(x, pc);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) out[p * stride + o + (int64_t)c * K + k] = (uint16_t)pc[p];
+      for (int p = 0; p < NP; ++p) out[p * stride + po + idx] = (uint16_t)pc[p];
     }
   }
 }
@@ -213,34 +201,25 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
     const uint64_t w1 = ((uint64_t)w1hi << 32) | w1lo;
     rec = load_rec();
     padvance();
-    const int K2 = (int)(w0 >> 48) * 2;
+    // rows of A and columns of B are padded with zeros to Kp (a multiple of
+    // 8), so a lane's group of 8 values is either past the step (no valid k:
+    // read as zero) or one aligned 16-byte load whose values past K are zero
+    const int K2 = (int)(w0 >> 48) * 2;      // Kp in bytes
     const int kv = live ? (int)(w1 >> 48) : 0;
-    const int cnt = min(max(kv - 8 * h, 0), 8);
-    // dword j holds the lane's values 2j, 2j + 1 (low half first)
-    uint32_t m[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) m[j] = cnt >= 2 * j + 2 ? 0xffffffffu : (cnt == 2 * j + 1 ? 0x0000ffffu : 0u);
+    const bool any = kv > 8 * h;
     const uint32_t ao = (uint32_t)(w0 & kMask48) + 16u * h;
     const uint32_t bo = (uint32_t)(w1 & kMask48) + 16u * h;
 #pragma unroll
     for (int x = 0; x < MX; ++x) {
-      const uint32_t o = (rowA[x] >= 0 && cnt > 0) ? ao + (uint32_t)(rowA[x] * K2) : kOobS;
+      const uint32_t o = (rowA[x] >= 0 && any) ? ao + (uint32_t)(rowA[x] * K2) : kOobS;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        u32x4 v = load16(ra, o + p * xpb);
-        v[0] &= m[0]; v[1] &= m[1]; v[2] &= m[2]; v[3] &= m[3];
-        a[x][p] = v;
-      }
+      for (int p = 0; p < NP; ++p) a[x][p] = load16(ra, o + p * xpb);
     }
 #pragma unroll
     for (int y = 0; y < MY; ++y) {
-      const uint32_t o = (colB[y] >= 0 && cnt > 0) ? bo + (uint32_t)(colB[y] * K2) : kOobS;
+      const uint32_t o = (colB[y] >= 0 && any) ? bo + (uint32_t)(colB[y] * K2) : kOobS;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        u32x4 v = load16(rb, o + p * ypb);
-        v[0] &= m[0]; v[1] &= m[1]; v[2] &= m[2]; v[3] &= m[3];
-        b[y][p] = v;
-      }
+      for (int p = 0; p < NP; ++p) b[y][p] = load16(rb, o + p * ypb);
     }
     const bool last = s + 2 >= se;
     flag = live ? (1 | (last ? 2 : 0)) : 0;
@@ -373,28 +352,19 @@ k_numeric_split(NumParams P, SplitWaves W) {
   }
 }
 
-hipError_t launch_split_rows(hipStream_t s, int npieces, const double* x, int64_t n, int64_t stride, uint16_t* out) {
-  if (stride <= 0) return hipSuccess;
-  if (stride % 4 != 0 || stride < n) return hipErrorInvalidValue;
-  const int64_t q = stride / 4;
-  const dim3 g((unsigned)((q + 255) / 256)), blk(256);
-  if (npieces == 2) hipLaunchKernelGGL((k_split_rows<2>), g, blk, 0, s, x, n, stride, out);
-  else hipLaunchKernelGGL((k_split_rows<3>), g, blk, 0, s, x, n, stride, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_split_cols(hipStream_t s, int npieces, const double* y, int64_t nblk, const int32_t* row,
-                             const int32_t* col, const int32_t* blk, const int64_t* off, const int32_t* rs,
-                             const int32_t* cs, int64_t n, int64_t stride, uint16_t* out) {
-  if (stride < n) return hipErrorInvalidValue;
+hipError_t launch_split_blocks(hipStream_t s, int npieces, const double* v, int64_t nblk, const int32_t* row,
+                               const int32_t* col, const int32_t* blk, const int64_t* off, const int64_t* pad,
+                               const int32_t* rs, const int32_t* cs, int trans, int64_t n, int64_t stride,
+                               uint16_t* out) {
+  if (stride < n || (npieces != 2 && npieces != 3)) return hipErrorInvalidValue;
   if (nblk > 0) {
     const int64_t groups = std::min<int64_t>((nblk + 3) / 4, 65536);
     if (npieces == 2)
-      hipLaunchKernelGGL((k_split_cols<2>), dim3((unsigned)groups), dim3(256), 0, s, y, nblk, row, col, blk, off, rs,
-                         cs, stride, out);
+      hipLaunchKernelGGL((k_split_blocks<2>), dim3((unsigned)groups), dim3(256), 0, s, v, nblk, row, col, blk, off,
+                         pad, rs, cs, trans, stride, out);
     else
-      hipLaunchKernelGGL((k_split_cols<3>), dim3((unsigned)groups), dim3(256), 0, s, y, nblk, row, col, blk, off, rs,
-                         cs, stride, out);
+      hipLaunchKernelGGL((k_split_blocks<3>), dim3((unsigned)groups), dim3(256), 0, s, v, nblk, row, col, blk, off,
+                         pad, rs, cs, trans, stride, out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -19,19 +19,44 @@ namespace {
 
 constexpr int kStepK = 16;
 
-// The two words of a step record.  FP64: byte offsets into the float64
-// values (A row-major, B row-major).  Split precision: byte offsets into the
-// bfloat16 piece arrays, A row-major, B blocks transposed (element (k, c) of
-// a K x N block at c * K + k).
-__device__ __forceinline__ void step_words(int64_t xo, int64_t yo, int K, int N, int r0, int c0, int k0,
+// Split precision: the block whose element offset is o (off ascending, the
+// block starts; n blocks), i.e. the last s with off[s] <= o.
+__device__ __forceinline__ int64_t block_at(const int64_t* off, int64_t n, int64_t o) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= o) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A product's operand bases: FP64, the element offsets themselves; split
+// precision, the blocks' offsets in the padded piece arrays.
+__device__ __forceinline__ void product_bases(int64_t xo, int64_t yo, const PieceMap& pm, int64_t& xb, int64_t& yb) {
+  if (!pm.apad) {
+    xb = xo;
+    yb = yo;
+  } else {
+    xb = pm.apad[block_at(pm.aoff, pm.na, xo)];
+    yb = pm.bpad[block_at(pm.boff, pm.nb, yo)];
+  }
+}
+
+// The two words of a step record (bases from product_bases).  FP64: byte
+// offsets into the float64 values (A and B row-major) and K.  Split
+// precision: byte offsets into the bfloat16 piece arrays (A rows and B
+// columns padded to Kp = K rounded up to 8: element (k, c) of a K x N block
+// of B at c * Kp + k) and Kp.
+__device__ __forceinline__ void step_words(int64_t xb, int64_t yb, int K, int N, int r0, int c0, int k0,
                                            bool split, uint64_t* out) {
   const uint64_t kv = (uint64_t)min(kStepK, K - k0);
   if (!split) {
-    out[0] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
-    out[1] = ((uint64_t)(yo + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
+    out[0] = ((uint64_t)(xb + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
+    out[1] = ((uint64_t)(yb + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
   } else {
-    out[0] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 2u) | ((uint64_t)K << 48);
-    out[1] = ((uint64_t)(yo + (int64_t)c0 * K + k0) * 2u) | (kv << 48);
+    const int Kp = (K + 7) & ~7;
+    out[0] = ((uint64_t)(xb + (int64_t)r0 * Kp + k0) * 2u) | ((uint64_t)Kp << 48);
+    out[1] = ((uint64_t)(yb + (int64_t)c0 * Kp + k0) * 2u) | (kv << 48);
   }
 }
 
@@ -127,7 +152,7 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
                              const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
                              const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
                              const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, const int64_t* __restrict__ chs, int split,
+                             const int32_t* __restrict__ cs, const int64_t* __restrict__ chs, PieceMap pm,
                              uint64_t* __restrict__ steps, TaskDesc* __restrict__ desc) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
@@ -163,9 +188,10 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
   if (M <= kTile && N <= kTile) return;  // written per product
   for (int64_t p = p0; p < p1; ++p) {
     const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
-    const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
+    int64_t xb, yb;
+    product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
     const int K = (int)(xw >> 48);
-    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xo, yo, K, N, r0, c0, k0, split != 0, steps + 2 * s);
+    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xb, yb, K, N, r0, c0, k0, pm.apad != nullptr, steps + 2 * s);
   }
 }
 
@@ -175,7 +201,7 @@ __global__ void k_product_steps(int64_t nprod, int64_t nblk, const int64_t* __re
                                 const int64_t* __restrict__ chs, const int32_t* __restrict__ blk2tile,
                                 const int64_t* __restrict__ sbase, const int32_t* __restrict__ c_col,
                                 const int32_t* __restrict__ cs, const int64_t* __restrict__ px,
-                                const int64_t* __restrict__ py, int split, uint64_t* __restrict__ steps) {
+                                const int64_t* __restrict__ py, PieceMap pm, uint64_t* __restrict__ steps) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprod) return;
   int64_t lo = 0, hi = nblk - 1;      // the block t with pptr[t] <= p < pptr[t + 1]
@@ -189,9 +215,10 @@ __global__ void k_product_steps(int64_t nprod, int64_t nblk, const int64_t* __re
   const int N = cs[c_col[t]];
   int64_t s = sbase[w] + (chs[p] - chs[pptr[t]]);
   const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
-  const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
+  int64_t xb, yb;
+  product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
   const int K = (int)(xw >> 48);
-  for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xo, yo, K, N, 0, 0, k0, split != 0, steps + 2 * s);
+  for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -224,21 +251,21 @@ hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const 
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, const int64_t* chs, bool split, uint64_t* steps,
-                             TaskDesc* desc) {
+                             const int32_t* rs, const int32_t* cs, const int64_t* chs, const PieceMap& pm,
+                             uint64_t* steps, TaskDesc* desc) {
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, chs, (int)split, steps, desc);
+                     c_col, c_off, cin_off, pptr, px, py, rs, cs, chs, pm, steps, desc);
   return hipGetLastError();
 }
 
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
                                 const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
                                 const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
-                                bool split, uint64_t* steps) {
+                                const PieceMap& pm, uint64_t* steps) {
   if (nprod == 0) return hipSuccess;
   hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, nblk, pptr,
-                     chs, blk2tile, sbase, c_col, cs, px, py, (int)split, steps);
+                     chs, blk2tile, sbase, c_col, cs, px, py, pm, steps);
   return hipGetLastError();
 }
 
