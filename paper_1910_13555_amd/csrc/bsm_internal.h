@@ -161,12 +161,6 @@ hipError_t launch_panel_order(hipStream_t s, int32_t ntiles, int2* tiles, const 
                               int32_t pc, void* scratch, int64_t scratch_bytes);
 // bsm_steps.hip: step lists of the row-major path (one work item per tile,
 // 16-byte step records; see the file's header).
-hipError_t launch_count_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* pptr,
-                              const int64_t* px, int64_t* nsteps);
-hipError_t launch_fill_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
-                             const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
-                             const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc);
 // Product-parallel step building: chunks per product; per-tile step counts
 // (and the single-tile block map); work items, empty-tile steps and steps of
 // multi-tile blocks; steps of single-tile blocks per product.

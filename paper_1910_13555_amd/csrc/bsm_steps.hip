@@ -60,67 +60,6 @@ __device__ __forceinline__ void step_words(int64_t xb, int64_t yb, int K, int N,
   }
 }
 
-__global__ void k_count_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ pptr,
-                              const int64_t* __restrict__ px, int64_t* __restrict__ nsteps) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= ntiles) return;
-  const int t = tiles[w].x;
-  int64_t n = 0;
-  for (int64_t p = pptr[t]; p < pptr[t + 1]; ++p) {
-    const int K = (int)((uint64_t)px[p] >> 48);
-    n += (K + kStepK - 1) / kStepK;
-  }
-  nsteps[w] = n > 0 ? n : 1;
-}
-
-__global__ void k_fill_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ sbase,
-                             const int32_t* __restrict__ c_row, const int32_t* __restrict__ c_col,
-                             const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
-                             const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
-                             const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, uint64_t* __restrict__ steps,
-                             TaskDesc* __restrict__ desc) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= ntiles) return;
-  const int t = tiles[w].x;
-  const int tr = tiles[w].y & 0xffff, tc = tiles[w].y >> 16;
-  const int i = c_row[t], j = c_col[t];
-  const int M = rs[i], N = cs[j];
-  const int r0 = tr * kTile, c0 = tc * kTile;
-  const int mt = min(kTile, M - r0), nt = min(kTile, N - c0);
-  int64_t s = sbase[w];
-  TaskDesc d;
-  d.pbeg = s;
-  d.cout = c_off[t];
-  d.cin = cin_off ? cin_off[t] : -1;
-  d.np = (int32_t)(sbase[w + 1] - s);
-  d.flags = kTaskFirst | kTaskLast | (pptr[t] == pptr[t + 1] ? kTaskEmpty : 0);
-  d.M = (uint16_t)M;
-  d.N = (uint16_t)N;
-  d.tr = (uint16_t)tr;
-  d.tc = (uint16_t)tc;
-  d.qo = 1;
-  d.cls = (uint16_t)tile_class(mt, nt);
-  d.pid = 0;
-  desc[w] = d;
-  const int64_t p0 = pptr[t], p1 = pptr[t + 1];
-  if (p0 == p1) {
-    steps[2 * s] = 0;
-    steps[2 * s + 1] = 0;
-    return;
-  }
-  for (int64_t p = p0; p < p1; ++p) {
-    const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
-    const int64_t xo = (int64_t)(xw & kMask48), yo = (int64_t)(yw & kMask48);
-    const int K = (int)(xw >> 48);
-    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) {
-      const uint64_t kv = (uint64_t)min(kStepK, K - k0);
-      steps[2 * s] = ((uint64_t)(xo + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
-      steps[2 * s + 1] = ((uint64_t)(yo + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
-    }
-  }
-}
-
 // Product-parallel form.  chunks[p] = ceil(K_p / 16) for every product.
 __global__ void k_product_chunks(int64_t nprod, const int64_t* __restrict__ px, int64_t* __restrict__ chunks) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,21 +208,5 @@ hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, cons
   return hipGetLastError();
 }
 
-hipError_t launch_count_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* pptr,
-                              const int64_t* px, int64_t* nsteps) {
-  if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, pptr, px, nsteps);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_steps(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
-                             const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
-                             const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, uint64_t* steps, TaskDesc* desc) {
-  if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, steps, desc);
-  return hipGetLastError();
-}
 
 }  // namespace bsm
