@@ -86,22 +86,18 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
   if (P.eps2 > 0.0) {  // the plan keeps its own norms: the gradient reuses the same test
     pl->na = DBuf<double>(ctx, A->nblk);
     pl->nb = DBuf<double>(ctx, B->nblk);
-    if (a_norms) {
-      if (A->nblk)
-        hip_check(hipMemcpyAsync(pl->na.p, a_norms, sizeof(double) * A->nblk, hipMemcpyDeviceToDevice, st),
-                  "copy norms A");
-    } else {
-      if (!a_vals && A->nblk) fail(BSM_E_INVALID, "filter_eps > 0 needs A values or norms");
-      hip_check(launch_block_norms(st, A->nblk, A->d_off.p, a_vals, pl->na.p), "norms A");
-    }
-    if (b_norms) {
-      if (B->nblk)
-        hip_check(hipMemcpyAsync(pl->nb.p, b_norms, sizeof(double) * B->nblk, hipMemcpyDeviceToDevice, st),
-                  "copy norms B");
-    } else {
-      if (!b_vals && B->nblk) fail(BSM_E_INVALID, "filter_eps > 0 needs B values or norms");
-      hip_check(launch_block_norms(st, B->nblk, B->d_off.p, b_vals, pl->nb.p), "norms B");
-    }
+    if (!a_norms && !a_vals && A->nblk) fail(BSM_E_INVALID, "filter_eps > 0 needs A values or norms");
+    if (!b_norms && !b_vals && B->nblk) fail(BSM_E_INVALID, "filter_eps > 0 needs B values or norms");
+    if (a_norms && A->nblk)
+      hip_check(hipMemcpyAsync(pl->na.p, a_norms, sizeof(double) * A->nblk, hipMemcpyDeviceToDevice, st),
+                "copy norms A");
+    if (b_norms && B->nblk)
+      hip_check(hipMemcpyAsync(pl->nb.p, b_norms, sizeof(double) * B->nblk, hipMemcpyDeviceToDevice, st),
+                "copy norms B");
+    // the norms still to compute, both operands in one launch
+    hip_check(launch_block_norms2(st, a_norms ? 0 : A->nblk, A->d_off.p, a_vals, pl->na.p, b_norms ? 0 : B->nblk,
+                                  B->d_off.p, b_vals, pl->nb.p),
+              "norms");
     P.a.nrm = pl->na.p;
     P.b.nrm = pl->nb.p;
   }
@@ -141,8 +137,11 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     hip_check(hipMemcpyAsync(pl->c_off.p, &z, sizeof z, hipMemcpyHostToDevice, st), "copy");
     hip_check(hipMemcpyAsync(pl->pptr.p, &z, sizeof z, hipMemcpyHostToDevice, st), "copy");
   }
+  // step-path plans: the output block of every product, for the step records
+  DBuf<int32_t> pblk(ctx, pl->step_path() ? pl->nprod : 0);
   hip_check(launch_sym_fill(st, P, base.p, pl->c_ptr.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
-                            pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p),
+                            pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p,
+                            pl->step_path() ? pblk.p : nullptr),
             "symbolic fill");
   pl->c_same_as_cin = C && pl->c_nblk == C->nblk;
   if (g_panel[0] > 0 && pl->ntasks > 1) {
@@ -191,7 +190,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                                 pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, chs.p,
                                 pm, pl->steps.p, pl->sdesc.p),
               "work items");
-    hip_check(launch_product_steps(st, pl->nprod, pl->c_nblk, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
+    hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
                                    pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
               "product steps");
   }

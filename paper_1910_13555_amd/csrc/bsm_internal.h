@@ -143,6 +143,9 @@ struct BwdParams {
 // bsm_symbolic.hip
 hipError_t launch_block_norms(hipStream_t s, int64_t nblk, const int64_t* off, const double* v,
                               double* out);
+// Norms of two operands in one launch (n = 0: none for that operand).
+hipError_t launch_block_norms2(hipStream_t s, int64_t na, const int64_t* offa, const double* va, double* outa,
+                               int64_t nb, const int64_t* offb, const double* vb, double* outb);
 hipError_t launch_sym_count(hipStream_t s, const SymParams& p, int64_t* cnt);
 // bsm_scan.hip: exclusive prefix sums of nf fields of n int64 counts
 // (in[f*n + r] -> out[f*(n+1) + r], totals at out[f*(n+1) + n] and tot[f] if
@@ -152,7 +155,8 @@ hipError_t launch_scan(hipStream_t s, int nf, int64_t n, const int64_t* in, int6
 int64_t scan_scratch_size(int nf, int64_t n);
 hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* base, int32_t* c_ptr,
                            int32_t* c_row, int32_t* c_col, int64_t* c_off, int64_t* cin_off_out,
-                           int64_t* pptr, int64_t* px, int64_t* py, int2* tasks);
+                           int64_t* pptr, int64_t* px, int64_t* py, int2* tasks,
+                           int32_t* pblk /* optional: output block of each product */);
 // bsm_order.hip: reorder a class-sorted tile list into 2-D panels of the
 // output block grid (pr x pc blocks), keeping the class ranges.
 int64_t panel_order_scratch_bytes(int64_t ntiles);
@@ -184,7 +188,7 @@ hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, c
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
                              const int32_t* rs, const int32_t* cs, const int64_t* chs, const PieceMap& pm,
                              uint64_t* steps, TaskDesc* desc);
-hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
+hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
                                 const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
                                 const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
                                 const PieceMap& pm, uint64_t* steps);

@@ -1,7 +1,10 @@
 // Exclusive prefix sums of int64 counts on the device: nf independent fields
 // of n counts each (in[f*n + r]) into out[f*(n+1) + r], with out[f*(n+1) + n]
-// and tot[f] the field total.  Three passes: per-workgroup scan of 2048
-// counts, scan of the workgroup totals, and the add-back.
+// and tot[f] the field total.  Several fields: three passes (per-workgroup
+// scan of 2048 counts, scan of the workgroup totals, add-back).  One field:
+// hipCUB's single-pass device scan over the n counts and a closing zero.
+#include <hipcub/hipcub.hpp>
+
 #include "bsm_internal.h"
 
 namespace bsm {
@@ -97,8 +100,40 @@ __global__ void __launch_bounds__(kScanT) k_scan_add(int64_t n, const int64_t* _
   }
 }
 
+namespace {
+
+// in[i] for i < n, 0 at i = n
+struct PadZero {
+  const int64_t* in;
+  int64_t n;
+  __host__ __device__ int64_t operator()(int64_t i) const { return i < n ? in[i] : 0; }
+};
+using PadIt = hipcub::TransformInputIterator<int64_t, PadZero, hipcub::CountingInputIterator<int64_t>>;
+
+size_t single_scan_bytes(int64_t n) {
+  size_t bytes = 0;
+  PadIt it(hipcub::CountingInputIterator<int64_t>(0), PadZero{nullptr, n});
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, (int64_t*)nullptr, (int)(n + 1));
+  return bytes;
+}
+
+__global__ void k_copy_total(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
+
+}  // namespace
+
 hipError_t launch_scan(hipStream_t s, int nf, int64_t n, const int64_t* in, int64_t* out, int64_t* tot,
                        int64_t* scratch) {
+  if (nf == 1 && n < (int64_t(1) << 31) - 1) {
+    size_t bytes = single_scan_bytes(n);
+    PadIt it(hipcub::CountingInputIterator<int64_t>(0), PadZero{in, n});
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(scratch, bytes, it, out, (int)(n + 1), s);
+    if (e != hipSuccess) return e;
+    if (tot) {
+      hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(1), 0, s, out + n, tot);
+      e = hipGetLastError();
+    }
+    return e;
+  }
   const int64_t nb = (n + kScanB - 1) / kScanB;
   if (nb > 0) {
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb, nf), dim3(kScanT), 0, s, n, in, out, scratch);
@@ -112,6 +147,10 @@ hipError_t launch_scan(hipStream_t s, int nf, int64_t n, const int64_t* in, int6
   return hipGetLastError();
 }
 
-int64_t scan_scratch_size(int nf, int64_t n) { return (int64_t)nf * std::max<int64_t>(1, (n + kScanB - 1) / kScanB); }
+int64_t scan_scratch_size(int nf, int64_t n) {
+  if (nf == 1 && n < (int64_t(1) << 31) - 1)
+    return std::max<int64_t>(1, (int64_t)((single_scan_bytes(n) + 7) / 8));
+  return (int64_t)nf * std::max<int64_t>(1, (n + kScanB - 1) / kScanB);
+}
 
 }  // namespace bsm

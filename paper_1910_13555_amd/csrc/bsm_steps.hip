@@ -136,19 +136,14 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
 
 // Per product of a single-tile block: its steps at the tile's base plus the
 // chunks of the block's earlier products.
-__global__ void k_product_steps(int64_t nprod, int64_t nblk, const int64_t* __restrict__ pptr,
+__global__ void k_product_steps(int64_t nprod, const int32_t* __restrict__ pblk, const int64_t* __restrict__ pptr,
                                 const int64_t* __restrict__ chs, const int32_t* __restrict__ blk2tile,
                                 const int64_t* __restrict__ sbase, const int32_t* __restrict__ c_col,
                                 const int32_t* __restrict__ cs, const int64_t* __restrict__ px,
                                 const int64_t* __restrict__ py, PieceMap pm, uint64_t* __restrict__ steps) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprod) return;
-  int64_t lo = 0, hi = nblk - 1;      // the block t with pptr[t] <= p < pptr[t + 1]
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (pptr[mid] <= p) lo = mid; else hi = mid - 1;
-  }
-  const int64_t t = lo;
+  const int64_t t = pblk[p];          // the block of product p
   const int w = blk2tile[t];
   if (w < 0) return;
   const int N = cs[c_col[t]];
@@ -198,12 +193,12 @@ hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, c
   return hipGetLastError();
 }
 
-hipError_t launch_product_steps(hipStream_t s, int64_t nprod, int64_t nblk, const int64_t* pptr,
+hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
                                 const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
                                 const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
                                 const PieceMap& pm, uint64_t* steps) {
   if (nprod == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, nblk, pptr,
+  hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, pblk, pptr,
                      chs, blk2tile, sbase, c_col, cs, px, py, pm, steps);
   return hipGetLastError();
 }

@@ -96,6 +96,62 @@ __global__ void __launch_bounds__(256) k_block_norms(int64_t nblk, const int64_t
   if (l == 0) out[b] = s;
 }
 
+// Both operands' norms in one launch, four blocks per wavefront with their
+// loads interleaved (more memory requests in flight per wavefront); each
+// block's arithmetic is exactly that of k_block_norms.
+constexpr int kNormBlocks = 4;
+__global__ void __launch_bounds__(256) k_block_norms2(int64_t na, const int64_t* __restrict__ offa,
+                                                      const double* __restrict__ va, double* __restrict__ outa,
+                                                      int64_t nb, const int64_t* __restrict__ offb,
+                                                      const double* __restrict__ vb, double* __restrict__ outb) {
+#pragma clang fp contract(off)
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t wa = (na + kNormBlocks - 1) / kNormBlocks;
+  const bool first = w < wa;
+  const int64_t n = first ? na : nb;
+  const int64_t b0 = (first ? w : w - wa) * kNormBlocks;
+  if (b0 >= n) return;
+  const int64_t* off = first ? offa : offb;
+  const double* v = first ? va : vb;
+  double* out = first ? outa : outb;
+  const int l = lane_id();
+  int64_t base[kNormBlocks], len[kNormBlocks];
+  int64_t lmax = 0;
+#pragma unroll
+  for (int q = 0; q < kNormBlocks; ++q) {
+    const bool has = b0 + q < n;
+    base[q] = has ? off[b0 + q] : 0;
+    len[q] = has ? off[b0 + q + 1] - base[q] : 0;
+    lmax = len[q] > lmax ? len[q] : lmax;
+  }
+  double s[kNormBlocks];
+#pragma unroll
+  for (int q = 0; q < kNormBlocks; ++q) s[q] = 0.0;
+  for (int64_t e = l; e < lmax; e += kWave) {
+    double x[kNormBlocks];
+#pragma unroll
+    for (int q = 0; q < kNormBlocks; ++q) x[q] = e < len[q] ? v[base[q] + e] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kNormBlocks; ++q)
+      if (e < len[q]) s[q] = __dadd_rn(s[q], __dmul_rn(x[q], x[q]));
+  }
+#pragma unroll
+  for (int q = 0; q < kNormBlocks; ++q) {
+#pragma unroll
+    for (int h = 32; h >= 1; h >>= 1) s[q] = __dadd_rn(s[q], __shfl_xor(s[q], h, kWave));
+    if (l == 0 && b0 + q < n) out[b0 + q] = s[q];
+  }
+}
+
+hipError_t launch_block_norms2(hipStream_t s, int64_t na, const int64_t* offa, const double* va, double* outa,
+                               int64_t nb, const int64_t* offb, const double* vb, double* outb) {
+  const int64_t waves = (na + kNormBlocks - 1) / kNormBlocks + (nb + kNormBlocks - 1) / kNormBlocks;
+  if (waves == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_norms2, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, na, offa, va, outa, nb,
+                     offb, vb, outb);
+  return hipGetLastError();
+}
+
 hipError_t launch_block_norms(hipStream_t s, int64_t nblk, const int64_t* off, const double* v,
                               double* out) {
   if (nblk == 0) return hipSuccess;
@@ -304,7 +360,8 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
                                                           int64_t* __restrict__ pptr,
                                                           int64_t* __restrict__ px,
                                                           int64_t* __restrict__ py,
-                                                          int2* __restrict__ tasks) {
+                                                          int2* __restrict__ tasks,
+                                                          int32_t* __restrict__ pblk) {
   __shared__ FillLds S;
   const int row = blockIdx.x;
   const int nr = P.a.nr, nc = P.b.nc;
@@ -435,6 +492,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
         const int ap = S.e.apos[c.e];
         px[g] = P.a.off[P.a.blk ? P.a.blk[ap] : ap] | ((int64_t)P.ks[c.k] << 48);
         py[g] = P.b.off[P.b.blk ? P.b.blk[c.bp] : c.bp];
+        if (pblk) pblk[g] = (int32_t)(rowblk0 + pos_base + q);
       }
       __syncthreads();
       for (int q = tid; q < npos; q += blockDim.x) S.cur[q] += __popcll(S.mask[q]);
@@ -450,10 +508,10 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
 
 hipError_t launch_sym_fill(hipStream_t s, const SymParams& p, const int64_t* base, int32_t* c_ptr,
                            int32_t* c_row, int32_t* c_col, int64_t* c_off, int64_t* cin_off_out,
-                           int64_t* pptr, int64_t* px, int64_t* py, int2* tasks) {
+                           int64_t* pptr, int64_t* px, int64_t* py, int2* tasks, int32_t* pblk) {
   if (p.a.nr == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sym_fill, dim3(p.a.nr), dim3(kSymThreads), 0, s, p, base, c_ptr, c_row, c_col,
-                     c_off, cin_off_out, pptr, px, py, tasks);
+                     c_off, cin_off_out, pptr, px, py, tasks, pblk);
   return hipGetLastError();
 }
 
