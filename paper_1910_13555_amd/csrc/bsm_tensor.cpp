@@ -182,9 +182,21 @@ std::vector<int32_t> block_dims(const bsm_tpattern_s& t) {
 }
 
 // Numbering of the occurring index tuples of a group of modes.
+// Numbering of the index tuples that occur (rows, columns or summed tuples of
+// the matricized operands), in lexicographic order.  A small tuple space is
+// numbered through a dense table (O(1) lookups); a large one through the
+// sorted list.
 struct TupleIndex {
   std::vector<Key> keys;  // sorted, unique
+  std::vector<int64_t> dims;   // blocks per mode of the tuple
+  std::vector<int32_t> table;  // dense: id of each linear tuple index, -1 if absent
+  int64_t lin(const Key& k) const {
+    int64_t v = 0;
+    for (size_t a = 0; a < dims.size(); ++a) v = v * dims[a] + k[a];
+    return v;
+  }
   int32_t id(const Key& k) const {
+    if (!table.empty()) return table[lin(k)];
     return (int32_t)(std::lower_bound(keys.begin(), keys.end(), k) - keys.begin());
   }
 };
@@ -208,7 +220,16 @@ std::unique_ptr<bsm_pattern_s> build_matrix(bsm_ctx ctx, const std::vector<int32
                                             const std::vector<int32_t>& cs,
                                             std::vector<std::array<int32_t, 3>>& ent,
                                             const std::vector<int64_t>& off, int64_t nvals) {
-  std::sort(ent.begin(), ent.end());
+  {  // canonical order: counting sort by row, then each row by (column, block)
+    std::vector<int64_t> start(rs.size() + 1, 0);
+    for (const auto& e : ent) start[e[0] + 1]++;
+    for (size_t r = 0; r < rs.size(); ++r) start[r + 1] += start[r];
+    std::vector<std::array<int32_t, 3>> sorted(ent.size());
+    std::vector<int64_t> cur(start.begin(), start.end() - 1);
+    for (const auto& e : ent) sorted[cur[e[0]]++] = e;
+    for (size_t r = 0; r < rs.size(); ++r) std::sort(sorted.begin() + start[r], sorted.begin() + start[r + 1]);
+    ent.swap(sorted);
+  }
   auto p = std::make_unique<bsm_pattern_s>();
   p->ctx = ctx;
   p->nbr = (int32_t)rs.size();
@@ -330,23 +351,42 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
   if (l1.lay == kLaySplit && l3.lay == kLaySplit && l1.split != l3.split) l3.lay = kLayRemap;
   // numbered row / column / inner tuples
   TupleIndex kidx;
-  for (int64_t b = 0; b < T1->nblocks; ++b) {
-    ext->rows.keys.push_back(sub_key(*T1, sp.s1, sp.free1, b));
-    kidx.keys.push_back(sub_key(*T1, sp.s1, sp.con, b));
-  }
-  for (int64_t b = 0; b < T2->nblocks; ++b) {
-    kidx.keys.push_back(sub_key(*T2, sp.s2, sp.con, b));
-    ext->cols.keys.push_back(sub_key(*T2, sp.s2, sp.free2, b));
-  }
-  if (T3)
-    for (int64_t b = 0; b < T3->nblocks; ++b) {
-      ext->rows.keys.push_back(sub_key(*T3, sp.out, sp.free1, b));
-      ext->cols.keys.push_back(sub_key(*T3, sp.out, sp.free2, b));
+  using Src = std::pair<const bsm_tpattern_s*, const std::string*>;
+  auto number = [&](TupleIndex& ti, const std::string& modes, std::initializer_list<Src> srcs) {
+    int64_t space = 1;
+    for (char c : modes) {
+      ti.dims.push_back(std::max<int64_t>(1, (int64_t)ms.of[(unsigned char)c].size()));
+      space = space > (int64_t(1) << 40) / ti.dims.back() ? (int64_t(1) << 40) : space * ti.dims.back();
     }
-  for (TupleIndex* ti : {&ext->rows, &ext->cols, &kidx}) {
-    std::sort(ti->keys.begin(), ti->keys.end());
-    ti->keys.erase(std::unique(ti->keys.begin(), ti->keys.end()), ti->keys.end());
-  }
+    if (space <= (int64_t(1) << 24)) {  // dense table (at most 64 MB)
+      ti.table.assign(space, -1);
+      for (const Src& s : srcs)
+        if (s.first)
+          for (int64_t b = 0; b < s.first->nblocks; ++b) ti.table[ti.lin(sub_key(*s.first, *s.second, modes, b))] = 0;
+      int32_t n = 0;
+      for (int64_t v = 0; v < space; ++v) {
+        if (ti.table[v] < 0) continue;
+        ti.table[v] = n++;
+        Key k = {0, 0, 0, 0};
+        int64_t x = v;
+        for (int a = (int)modes.size() - 1; a >= 0; --a) {
+          k[a] = (int32_t)(x % ti.dims[a]);
+          x /= ti.dims[a];
+        }
+        ti.keys.push_back(k);
+      }
+    } else {
+      for (const Src& s : srcs)
+        if (s.first)
+          for (int64_t b = 0; b < s.first->nblocks; ++b) ti.keys.push_back(sub_key(*s.first, *s.second, modes, b));
+      std::sort(ti.keys.begin(), ti.keys.end());
+      ti.keys.erase(std::unique(ti.keys.begin(), ti.keys.end()), ti.keys.end());
+      ti.dims.clear();
+    }
+  };
+  number(ext->rows, sp.free1, {Src(T1, &sp.s1), Src(T3, &sp.out)});
+  number(kidx, sp.con, {Src(T1, &sp.s1), Src(T2, &sp.s2)});
+  number(ext->cols, sp.free2, {Src(T2, &sp.s2), Src(T3, &sp.out)});
   auto sizes_of = [&](const TupleIndex& ti, const std::string& modes, const char* what) {
     std::vector<int32_t> v(ti.keys.size());
     for (size_t i = 0; i < v.size(); ++i) {
@@ -360,6 +400,8 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
   const std::vector<int32_t> ksz = sizes_of(kidx, sp.con, "summed");
   const std::vector<int32_t> csz = sizes_of(ext->cols, sp.free2, "column");
   std::vector<std::array<int32_t, 3>> e1, e2, e3;
+  e1.reserve(T1->nblocks);
+  e2.reserve(T2->nblocks);
   for (int64_t b = 0; b < T1->nblocks; ++b)
     e1.push_back({ext->rows.id(sub_key(*T1, sp.s1, sp.free1, b)), kidx.id(sub_key(*T1, sp.s1, sp.con, b)), (int32_t)b});
   for (int64_t b = 0; b < T2->nblocks; ++b)
