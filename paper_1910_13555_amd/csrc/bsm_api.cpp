@@ -190,6 +190,10 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                                 pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, chs.p,
                                 pm, pl->steps.p, pl->sdesc.p),
               "work items");
+    ClassBounds cb;
+    std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, cb.cls);
+    pl->xb = DBuf<int32_t>(ctx, 9 * kClasses);
+    hip_check(launch_xcd_bounds(st, pl->sdesc.p, nullptr, cb, pl->xb.p), "XCD shares");
     hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
                                    pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
               "product steps");
@@ -272,6 +276,7 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
     P.desc = pl->sdesc.p;
     P.seg = nullptr;
     P.steps = pl->steps.p;
+    P.xb = pl->xb.p;
   }
   std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;

@@ -18,6 +18,7 @@ struct bsm_batch_s {
   int32_t precision = BSM_PREC_FP64;
   bool steps = false;  // the plans take the row-major step path
   DBuf<TaskDesc> desc;
+  DBuf<int32_t> xb;    // row-major path: XCD share bounds, 9 per class
   int32_t cls_tile[kClasses + 1] = {0};
   DBuf<ProbPtrs> ptab;
   std::vector<ProbPtrs> hptab;
@@ -111,6 +112,17 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
   for (int32_t p = 0; p < n; ++p)
     hip_check(launch_merge_desc(st, b->steps ? b->plans[p]->sdesc.p : b->plans[p]->desc.p, rng[p], p, b->desc.p),
               "merge work items");
+  if (b->steps) {  // step prefix of the merged list (the kernels cut XCD shares by steps)
+    DBuf<int64_t> np(ctx, total);
+    hip_check(launch_desc_steps(st, b->desc.p, total, np.p), "work item steps");
+    DBuf<int64_t> wpre(ctx, total + 1);
+    DBuf<int64_t> scr(ctx, scan_scratch_size(1, total));
+    hip_check(launch_scan(st, 1, total, np.p, wpre.p, nullptr, scr.p), "work item step prefix");
+    ClassBounds cb;
+    std::copy(b->cls_tile, b->cls_tile + kClasses + 1, cb.cls);
+    b->xb = DBuf<int32_t>(ctx, 9 * kClasses);
+    hip_check(launch_xcd_bounds(st, b->desc.p, wpre.p, cb, b->xb.p), "XCD shares");
+  }
   b->ptab = DBuf<ProbPtrs>(ctx, n);
   if (b->precision != BSM_PREC_FP64) {
     const int np = split_pieces(b->precision);
@@ -183,6 +195,7 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   P.seg = nullptr;
   std::copy(b->cls_tile, b->cls_tile + kClasses + 1, P.cls_tile);
   P.ptab = b->ptab.p;
+  P.xb = b->xb.p;
   for (int32_t p = 0; p < n; ++p) P.has_cin |= (t[p].beta != 0.0 && t[p].cin != nullptr) ? 1 : 0;
   P.ncu = ctx->ncu;
   P.mx = b->mx;

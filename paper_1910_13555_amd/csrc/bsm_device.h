@@ -106,4 +106,15 @@ __device__ __forceinline__ int slice_start(const TaskDesc* desc, int64_t d0, int
   return (int)s;
 }
 
+// Row-major path: the XCD shares of a class's items, computed once per plan
+// or batch (bsm_numeric.hip): items [xb[9c + x], xb[9c + x + 1]) of class c
+// go to XCD x, each share holding an eighth of the class's steps.
+__device__ __forceinline__ int xcd_bound(const NumParams& P, int c, int x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return cptr(P.xb)[__builtin_amdgcn_readfirstlane(9 * c + x)];
+#else
+  return P.xb[9 * c + x];  // host pass: never executed
+#endif
+}
+
 }  // namespace bsm

@@ -429,6 +429,7 @@ struct bsm_plan_s {
   // row-major FP64 plans: step records (2 words each) and one work item per tile
   DBuf<uint64_t> steps;
   DBuf<TaskDesc> sdesc;
+  DBuf<int32_t> xb;   // XCD share bounds of the items, 9 per class
   int64_t nsteps = 0;
   // split precision: stored-block offsets of A and B in the padded piece
   // layout (nblk + 1 each; the last entry is the padded size)

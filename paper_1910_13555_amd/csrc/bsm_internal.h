@@ -108,6 +108,7 @@ struct NumParams {
   int32_t inplace_skip = 0;       // out == cin, beta == 1: blocks without products untouched
   int32_t has_cin = 0;            // batches: some problem adds beta * C_in
   uint32_t xpb = 0, ypb = 0;      // split precision: X / Y are piece arrays of this many bytes each
+  const int32_t* xb = nullptr;    // row-major path: XCD share bounds, 9 per class (launch_xcd_bounds)
   hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
   int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran
   // optional: side streams (kNumericKernels - 1) on which families after the
@@ -224,6 +225,18 @@ struct MergeRanges {
   int64_t sbeg[kClasses + 1];
   int64_t dbeg[kClasses];
 };
+// Step count (np) of each of n work items into out[0..n).
+hipError_t launch_desc_steps(hipStream_t s, const TaskDesc* d, int64_t n, int64_t* out);
+// XCD share bounds of the row-major path: for each class c and x = 0..8,
+// xb[9c + x] = the first item of class c (items [cls[c], cls[c+1])) before
+// which at least x / 8 of the class's steps lie.  Steps before item i:
+// wpre[i] if given, else the items' own first-step numbers (a single plan
+// numbers its steps in item order).
+struct ClassBounds {
+  int32_t cls[kClasses + 1];
+};
+hipError_t launch_xcd_bounds(hipStream_t s, const TaskDesc* desc, const int64_t* wpre, const ClassBounds& cb,
+                             int32_t* xb);
 hipError_t launch_merge_desc(hipStream_t s, const TaskDesc* src, const MergeRanges& r, int32_t pid,
                              TaskDesc* dst);
 // Work items from a tile list {block, tile row | tile col << 16}: count the

@@ -10,7 +10,7 @@ int32_t g_variant[kClasses] = {0, 0, 0, 0, 0, 1, 0, 1, 0, 0, 0, 0, 0, 1, 0, 1};
 
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p) {
   if (p.cls_tile[kClasses] == 0) return hipSuccess;
-  if (!p.desc || p.ncu <= 0) return hipErrorInvalidValue;
+  if (!p.desc || p.ncu <= 0 || (!generic && !p.xb)) return hipErrorInvalidValue;
   const bool batch = p.ptab != nullptr;
   const bool cin = batch ? p.has_cin != 0 : (p.beta != 0.0 && p.cin != nullptr);
   // the generic path reads C_in in its epilogue: no read-ahead variant
@@ -109,6 +109,50 @@ hipError_t launch_merge_desc(hipStream_t s, const TaskDesc* src, const MergeRang
   const int64_t n = r.sbeg[kClasses];
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_desc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, r, pid, dst);
+  return hipGetLastError();
+}
+
+// Step count of every work item (for the batch's step prefix).
+__global__ void k_desc_steps(const TaskDesc* __restrict__ d, int64_t n, int64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = d[i].np;
+}
+
+hipError_t launch_desc_steps(hipStream_t s, const TaskDesc* d, int64_t n, int64_t* out) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_desc_steps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n, out);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ int64_t steps_before(const TaskDesc* d, const int64_t* wpre, int i, int d1) {
+  if (wpre) return wpre[i];
+  if (i < d1) return d[i].pbeg;
+  return d[d1 - 1].pbeg + d[d1 - 1].np;
+}
+
+__global__ void k_xcd_bounds(const TaskDesc* __restrict__ desc, const int64_t* __restrict__ wpre, ClassBounds cb,
+                             int32_t* __restrict__ xb) {
+  const int t = threadIdx.x;
+  if (t >= 9 * kClasses) return;
+  const int c = t / 9, x = t % 9;
+  const int d0 = cb.cls[c], d1 = cb.cls[c + 1];
+  int r = x == 0 ? d0 : d1;
+  if (x > 0 && x < 8 && d1 > d0) {
+    const int64_t w0 = steps_before(desc, wpre, d0, d1), w1 = steps_before(desc, wpre, d1, d1);
+    const int64_t target = w0 + (w1 - w0) * x / 8;
+    int lo = d0, hi = d1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (steps_before(desc, wpre, mid, d1) >= target) hi = mid; else lo = mid + 1;
+    }
+    r = lo;
+  }
+  xb[t] = r;
+}
+
+hipError_t launch_xcd_bounds(hipStream_t s, const TaskDesc* desc, const int64_t* wpre, const ClassBounds& cb,
+                             int32_t* xb) {
+  hipLaunchKernelGGL(k_xcd_bounds, dim3(1), dim3(9 * kClasses), 0, s, desc, wpre, cb, xb);
   return hipGetLastError();
 }
 

@@ -660,7 +660,14 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
   const int x = w % kXcd, r = w / kXcd;
   const int64_t d0 = P.seg ? P.seg[P.cls_tile[c]] : P.cls_tile[c];
   const int64_t d1 = P.seg ? P.seg[P.cls_tile[c + 1]] : P.cls_tile[c + 1];
-  const int e0 = slice_start(P.desc, d0, d1, x, kXcd), e1 = slice_start(P.desc, d0, d1, x + 1, kXcd);
+  int e0, e1;
+  if constexpr (GEN) {
+    e0 = slice_start(P.desc, d0, d1, x, kXcd);
+    e1 = slice_start(P.desc, d0, d1, x + 1, kXcd);
+  } else {  // one item per tile: XCD shares of equal step counts
+    e0 = xcd_bound(P, c, x);
+    e1 = xcd_bound(P, c, x + 1);
+  }
   if (e0 + r >= e1) return;
   constexpr int V = kKernVariant[KID];
   constexpr int DP = GEN ? kKernDepth[KID] : kStepDepth[KID];

@@ -330,8 +330,9 @@ struct SplitBudget {
 }  // namespace
 
 // Persistent kernel: wavefronts [w[c], w[c+1]) serve class c; local
-// wavefront w runs on XCD w % 8, each XCD owns a contiguous eighth of the
-// class's tiles and its wavefronts take them cyclically.
+// wavefront w runs on XCD w % 8, each XCD owns a contiguous share of the
+// class's tiles holding an eighth of its steps, and its wavefronts take them
+// cyclically.
 template <int NP, bool CIN, bool BATCH>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SplitBudget<NP>::waves)))
 k_numeric_split(NumParams P, SplitWaves W) {
@@ -341,8 +342,7 @@ k_numeric_split(NumParams P, SplitWaves W) {
   const int n = W.w[c + 1] - W.w[c];
   const int w = b - W.w[c];
   const int x = w % kXcd, r = w / kXcd;
-  const int64_t d0 = P.cls_tile[c], d1 = P.cls_tile[c + 1];
-  const int e0 = (int)(d0 + x * (d1 - d0) / kXcd), e1 = (int)(d0 + (x + 1) * (d1 - d0) / kXcd);
+  const int e0 = xcd_bound(P, c, x), e1 = xcd_bound(P, c, x + 1);
   if (e0 + r >= e1) return;
   switch (split_mx(c) * 2 + split_my(c)) {
     case 3: run_split_steps<1, 1, NP, CIN, BATCH, kSplitDepth>(P, e0, e1, r, n / kXcd); break;
@@ -375,7 +375,8 @@ hipError_t launch_split_blocks(hipStream_t s, int npieces, const double* v, int6
 
 hipError_t launch_numeric_split(hipStream_t s, int npieces, const NumParams& p) {
   if (p.cls_tile[kClasses] == 0) return hipSuccess;
-  if (!p.desc || !(p.steps || p.ptab) || p.ncu <= 0 || (npieces != 2 && npieces != 3)) return hipErrorInvalidValue;
+  if (!p.desc || !p.xb || !(p.steps || p.ptab) || p.ncu <= 0 || (npieces != 2 && npieces != 3))
+    return hipErrorInvalidValue;
   if (p.mx != kRowMajor || p.my != kRowMajor || p.mo != kRowMajor) return hipErrorInvalidValue;
   const int resident = p.ncu * 4 * (npieces == 2 ? SplitBudget<2>::waves : SplitBudget<3>::waves);
   // wavefronts per class in proportion to tiles x padded area, multiples of 8

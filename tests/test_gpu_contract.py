@@ -141,3 +141,35 @@ def test_rank3_ten_block_finite_differences(bsm):
         mm[e] -= 1.0
         fd = (L(Tl.values, mp) - L(Tl.values, mm)) / 2
         assert abs(fd - float(dM[e])) <= 1e-11 * (1 + abs(fd))
+
+
+def sparse_tensor(rng, mode_sizes, nblocks):
+    """A few blocks at random slots of a tensor with many blocks per mode
+    (lexicographic order, U[-1,1] values), without enumerating every slot."""
+    nbs = [len(s) for s in mode_sizes]
+    slots = set()
+    while len(slots) < nblocks:
+        slots.add(tuple(int(rng.integers(0, n)) for n in nbs))
+    idx = np.array(sorted(slots), np.int32)
+    lens = np.ones(len(idx), np.int64)
+    for m, s in enumerate(mode_sizes):
+        lens *= np.asarray(s, np.int64)[idx[:, m]]
+    return dict(mode_sizes=[np.asarray(s, np.int32) for s in mode_sizes], idx=idx,
+                values=rng.uniform(-1.0, 1.0, size=int(lens.sum())))
+
+
+def test_contract_large_tuple_space(bsm):
+    """Free modes of 5000 blocks each: the row tuple space (25 M) is numbered
+    through the sorted tuple list instead of a dense table."""
+    rng = np.random.default_rng(77)
+    sa = rng.choice([1, 2], size=5000).astype(np.int32)
+    sb = rng.choice([1, 3], size=5000).astype(np.int32)
+    sc = np.array([2, 3, 4], np.int32)
+    sd = np.array([1, 2, 5, 3], np.int32)
+    d1 = sparse_tensor(rng, [sa, sb, sc], 60)
+    d2 = sparse_tensor(rng, [sc, sd], 8)
+    R = bsm.contract("abc,cd->abd", to_lib(bsm, d1), to_lib(bsm, d2))
+    torch.cuda.synchronize()
+    ref, pairs = ot.contract(to_ref(d1), to_ref(d2), "abc,cd->abd")
+    assert R.plan.info["nprod"] == len(pairs)
+    assert_tensor_close(tensor_to_oracle(R.pattern, R.values, ref.mode_sizes), ref, TOL)
