@@ -188,7 +188,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
     hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
                                 pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, chs.p,
-                                pm, pl->steps.p, pl->sdesc.p),
+                                pl->rowq.p, pm, pl->steps.p, pl->sdesc.p),
               "work items");
     ClassBounds cb;
     std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, cb.cls);
@@ -269,7 +269,7 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
   P.my = pl->my;
   P.mo = pl->mo;
   P.inplace_skip = (out == cin && beta == 1.0) ? 1 : 0;
-  const bool generic = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
+  const bool generic = !pl->step_path();
   P.desc = pl->desc.p;
   P.seg = pl->seg.p;
   if (pl->step_path()) {  // one work item per tile, operands addressed by step records

@@ -67,7 +67,7 @@ bsm_batch make_batch(bsm_ctx ctx, int32_t n, const bsm_plan* plans) {
     if (!pl) fail(BSM_E_INVALID, "NULL plan %d", p);
     if (pl->ctx != ctx) fail(BSM_E_INVALID, "plan %d belongs to another context", p);
     if (pl->ext) fail(BSM_E_UNSUPPORTED, "plan %d needs layout remaps; batch matrix plans only", p);
-    const bool gen = pl->mx != kRowMajor || pl->my != kRowMajor || pl->mo != kRowMajor || pl->rowq.p;
+    const bool gen = !pl->step_path();
     if (p == 0) {
       b->generic = gen; b->mx = pl->mx; b->my = pl->my; b->mo = pl->mo; b->precision = pl->opts.precision;
     } else if (pl->mx != b->mx || pl->my != b->my || pl->mo != b->mo || gen != b->generic) {

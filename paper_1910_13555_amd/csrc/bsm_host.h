@@ -435,8 +435,12 @@ struct bsm_plan_s {
   // layout (nblk + 1 each; the last entry is the padded size)
   DBuf<int64_t> apad, bpad;
   int64_t apad_n = 0, bpad_n = 0;
-  bool step_path() const {  // row-major operands and output (FP64 or split precision)
-    return mx == bsm::kRowMajor && my == bsm::kRowMajor && mo == bsm::kRowMajor && !rowq.p;
+  // row-major operands (FP64 or split precision); output row-major, or in
+  // split rows (tensor layouts, FP64)
+  bool step_path() const {
+    if (mx != bsm::kRowMajor || my != bsm::kRowMajor) return false;
+    if (mo == bsm::kRowMajor) return !rowq.p;
+    return mo == bsm::kRowSplit && rowq.p && opts.precision == BSM_PREC_FP64;
   }
   DBuf<int32_t> rowq;  // split factors for tensor layouts (optional)
   DBuf<double> na, nb; // stored-block norms of A and B (kept for the gradient when filtering)

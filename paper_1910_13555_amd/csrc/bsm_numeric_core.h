@@ -480,11 +480,20 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   u32x4 R[D];                              // record of the step issued next into this buffer
   // per buffer: flags (1 live, 2 tile's last step, 4 k-steps 2-3 needed) and
   // the epilogue's fields of the tile
-  int tflag[D], tpid[D], tmn[D], ttile[D];
+  int tflag[D], tpid[D], tmn[D], ttile[D], tq[D];
+  // output element (r, c) of an M x N block: row-major, or split rows
+  // (r = u q + p stored at (u N + c) q + p; the tile's q travels with it)
+  const bool osplit = P.mo == kRowSplit;
+  auto oel = [&](int r, int c, int N, int q) __attribute__((always_inline)) {
+    if (!osplit) return r * N + c;
+    const int u = r / q;
+    return (u * N + c) * q + (r - u * q);
+  };
   int64_t tcout[D];
 
   auto issue = [&](double (&a)[NI][4], double (&b)[NJ][4], double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1],
-                   u32x4& rec, int& flag, int& pid, int& mn, int& tile, int64_t& cout) __attribute__((always_inline)) {
+                   u32x4& rec, int& flag, int& pid, int& mn, int& tile, int64_t& cout, int& tileq)
+                   __attribute__((always_inline)) {
     const bool live = it < e1;
     const uint64_t w0 = ((uint64_t)rec[1] << 32) | rec[0];
     const uint64_t w1 = ((uint64_t)rec[3] << 32) | rec[2];
@@ -540,7 +549,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
           for (int e = 0; e < NE; ++e) {
             const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
             const int cc = bcol(y);
-            const uint32_t off = (rr < mt && cc < nt) ? (uint32_t)((r0 + rr) * id.N + c0 + cc) * 8u : kOob;
+            const uint32_t off = (rr < mt && cc < nt) ? (uint32_t)oel(r0 + rr, c0 + cc, id.N, id.qo) * 8u : kOob;
             cb[x][y][e] = buf_load(rc, off);
           }
     }
@@ -548,6 +557,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     pid = id.pid;
     mn = (int)id.M | ((int)id.N << 16);
     tile = (int)id.tr | ((int)id.tc << 16) | ((id.flags & kTaskEmpty) ? (1 << 31) : 0);
+    tileq = (int)id.qo;
     cout = id.cout;
     if (!live) return;
     if (++s < se) return;
@@ -566,7 +576,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   for (int x = 0; x < NI; ++x)
 #pragma unroll
     for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
-  auto epilogue = [&](const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1], int pid, int mn, int tile,
+  auto epilogue = [&](const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1], int pid, int mn, int tile, int tileq,
                       int64_t cout) __attribute__((always_inline)) {
     const int M = mn & 0xffff, N = mn >> 16;
     const int er0 = (tile & 0xffff) * kTile, ec0 = ((tile >> 16) & 0x7fff) * kTile;
@@ -589,7 +599,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
             if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
             // branch-free: lanes outside the tile get an offset past the block
             const uint32_t in = (uint32_t)((rr - emt) & (cc - ent)) >> 31;   // rr < emt && cc < ent
-            const uint32_t off = ((uint32_t)((er0 + rr) * N + ec0 + cc) * 8u) | ((in ^ 1u) << 31);
+            const uint32_t off = ((uint32_t)oel(er0 + rr, ec0 + cc, N, tileq) * 8u) | ((in ^ 1u) << 31);
             double v = pp.alpha * av;
             if constexpr (PRE) {
               if (use_cin) v += pp.beta * cb[x][y][e];   // zero where the tile has no C_in block
@@ -626,7 +636,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     padvance();
   }
 #pragma unroll
-  for (int d = 0; d < D; ++d) issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d]);
+  for (int d = 0; d < D; ++d) issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d], tq[d]);
   // One exit, at the top: a wavefront's buffers go dead in issue order, so
   // buffer 0 dead means all are; a dead buffer after the last live one holds
   // zeros and adds nothing.  (An exit between the buffers would join the loop
@@ -637,8 +647,8 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       compute(A[d], B[d], (tflag[d] & 4) != 0);
-      if (tflag[d] & 2) epilogue(Cb[d], tpid[d], tmn[d], ttile[d], tcout[d]);
-      issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d]);
+      if (tflag[d] & 2) epilogue(Cb[d], tpid[d], tmn[d], ttile[d], tq[d], tcout[d]);
+      issue(A[d], B[d], Cb[d], R[d], tflag[d], tpid[d], tmn[d], ttile[d], tcout[d], tq[d]);
     }
   }
 }

@@ -91,8 +91,9 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
                              const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
                              const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
                              const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, const int64_t* __restrict__ chs, PieceMap pm,
-                             uint64_t* __restrict__ steps, TaskDesc* __restrict__ desc) {
+                             const int32_t* __restrict__ cs, const int64_t* __restrict__ chs,
+                             const int32_t* __restrict__ rowq, PieceMap pm, uint64_t* __restrict__ steps,
+                             TaskDesc* __restrict__ desc) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
   const int t = tiles[w].x;
@@ -113,7 +114,7 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
   d.N = (uint16_t)N;
   d.tr = (uint16_t)tr;
   d.tc = (uint16_t)tc;
-  d.qo = 1;
+  d.qo = (uint16_t)(rowq ? rowq[i] : 1);
   d.cls = (uint16_t)tile_class(mt, nt);
   d.pid = 0;
   desc[w] = d;
@@ -185,11 +186,11 @@ hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const 
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, const int64_t* chs, const PieceMap& pm,
-                             uint64_t* steps, TaskDesc* desc) {
+                             const int32_t* rs, const int32_t* cs, const int64_t* chs, const int32_t* rowq,
+                             const PieceMap& pm, uint64_t* steps, TaskDesc* desc) {
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, chs, pm, steps, desc);
+                     c_col, c_off, cin_off, pptr, px, py, rs, cs, chs, rowq, pm, steps, desc);
   return hipGetLastError();
 }
 

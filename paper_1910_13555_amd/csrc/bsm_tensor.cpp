@@ -348,6 +348,10 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
   LayoutChoice l1 = choose_layout(sp.s1, sp.free1, sp.con, true, true);
   LayoutChoice l2 = choose_layout(sp.s2, sp.con, sp.free2, true, false);
   LayoutChoice l3 = choose_layout(sp.out, sp.free1, sp.free2, false, true);
+  // The first operand in split rows is permuted to row-major when the rest
+  // allows the row-major kernels (their epilogue writes split output rows):
+  // one pass over that operand instead of every product's strided reads.
+  if (l1.lay == kLaySplit && l2.lay == kLayRM && (l3.lay == kLayRM || l3.lay == kLaySplit)) l1.lay = kLayRemap;
   if (l1.lay == kLaySplit && l3.lay == kLaySplit && l1.split != l3.split) l3.lay = kLayRemap;
   // numbered row / column / inner tuples
   TupleIndex kidx;
