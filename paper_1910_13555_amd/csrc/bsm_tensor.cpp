@@ -7,10 +7,12 @@
 // sizes); the matrix blocks stay where the tensor stores them.  Operands whose
 // storage order already matches the matrix layout -- row-major, transposed,
 // or the summed modes sitting between two groups of free modes -- are read
-// and written in place through the numeric kernel's layout modes; any other
-// operand is permuted block by block by the remap kernel into a scratch
-// buffer (the paper's conversion step, avoided when the caller picks a
-// compatible layout).
+// and written in place through the numeric kernel's layout modes, except a
+// first operand in the last form when the rest allows the row-major kernels:
+// it is permuted to row-major (one pass over it) so that those run.  Any
+// other operand is permuted block by block by the remap kernel into a
+// scratch buffer (the paper's conversion step, avoided when the caller picks
+// a compatible layout).
 #include <array>
 #include <string>
 
