@@ -399,8 +399,9 @@ void build_grad_lists(bsm_plan pl, int which) {
   L.px = DBuf<int64_t>(ctx, total);
   L.py = DBuf<int64_t>(ctx, total);
   hip_check(launch_bwd_lists(st, P, true, nullptr, L.pptr.p, L.px.p, L.py.p), "gradient fill");
+  L.max_tiles = max_tiles(grs, gcs);
   build_desc(ctx, nt, L.tasks.p, L.g_row.p, L.g_col.p, L.g_off.p, nullptr, L.pptr.p, L.rs.p, L.cs.p,
-             which == 0 ? pl->rowq.p : nullptr, total, max_tiles(grs, gcs), L.seg, L.desc);
+             which == 0 ? pl->rowq.p : nullptr, total, L.max_tiles, L.seg, L.desc);
   hip_check(hipStreamSynchronize(st), "gradient lists");
   L.ngroups = ng;
   L.nprod = total;
@@ -440,6 +441,19 @@ void execute_grad(bsm_plan pl, int which, double alpha, const double* x, const d
   P.seg = L.seg.p;
   std::copy(L.cls_tile, L.cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
+  // split-K when the tiles hold many segments on average (few output tiles,
+  // long product lists: e.g. the gradient of a small operand)
+  const int64_t segs = (L.nprod + 63) / 64;          // segments of at most 64 products
+  const int64_t cap = L.ntasks + L.max_tiles * segs;   // work items, at most
+  if (segs >= 4 * L.ntasks && cap * kTile * kTile * 8 <= (int64_t(8) << 30)) {
+    DBuf<double> part(pl->ctx, (size_t)cap * kTile * kTile);
+    P.part = part.p;
+    hip_check(launch_numeric(pl->ctx->stream, true, P), "gradient numeric");
+    hip_check(launch_reduce_parts(pl->ctx->stream, L.ntasks, L.seg.p, L.desc.p, part.p, alpha, 0.0, nullptr, out,
+                                  P.mo),
+              "gradient split-K");
+    return;
+  }
   hip_check(launch_numeric(pl->ctx->stream, true, P), "gradient numeric");
 }
 

@@ -447,7 +447,7 @@ struct bsm_plan_s {
   // gradient product lists, built on first use: [0] = dA, [1] = dB
   struct Lists {
     bool built = false;
-    int64_t ngroups = 0, nprod = 0, ntasks = 0;
+    int64_t ngroups = 0, nprod = 0, ntasks = 0, max_tiles = 1;
     DBuf<int32_t> g_row, g_col, rs, cs;
     DBuf<int64_t> g_off, pptr, px, py;
     DBuf<int2> tasks;

@@ -109,6 +109,7 @@ struct NumParams {
   int32_t has_cin = 0;            // batches: some problem adds beta * C_in
   uint32_t xpb = 0, ypb = 0;      // split precision: X / Y are piece arrays of this many bytes each
   const int32_t* xb = nullptr;    // row-major path: XCD share bounds, 9 per class (launch_xcd_bounds)
+  double* part = nullptr;         // generic path, split-K: kTile * kTile partial sums per work item
   hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
   int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran
   // optional: side streams (kNumericKernels - 1) on which families after the
@@ -226,6 +227,12 @@ struct MergeRanges {
   int64_t sbeg[kClasses + 1];
   int64_t dbeg[kClasses];
 };
+// Split-K epilogue of the generic path: per tile w (work items
+// [seg[w], seg[w+1]) with their partial sums in part, kTile * kTile each),
+// out = alpha * sum + beta * C_in in layout mo.
+hipError_t launch_reduce_parts(hipStream_t s, int64_t ntiles, const int64_t* seg, const TaskDesc* desc,
+                               const double* part, double alpha, double beta, const double* cin, double* out,
+                               int32_t mo);
 // Step count (np) of each of n work items into out[0..n).
 hipError_t launch_desc_steps(hipStream_t s, const TaskDesc* d, int64_t n, int64_t* out);
 // XCD share bounds of the row-major path: for each class c and x = 0..8,

@@ -156,6 +156,46 @@ hipError_t launch_xcd_bounds(hipStream_t s, const TaskDesc* desc, const int64_t*
   return hipGetLastError();
 }
 
+// Split-K: one workgroup per tile adds its segments' partial sums in segment
+// order (deterministic), then C = alpha * sum + beta * C_in in the output
+// layout.
+__global__ void __launch_bounds__(256) k_reduce_parts(const int64_t* __restrict__ seg,
+                                                      const TaskDesc* __restrict__ desc,
+                                                      const double* __restrict__ part, double alpha, double beta,
+                                                      const double* __restrict__ cin, double* __restrict__ out,
+                                                      int32_t mo) {
+  const int64_t w = blockIdx.x;
+  const int64_t s0 = seg[w], s1 = seg[w + 1];
+  const TaskDesc d = desc[s0];
+  const int r0 = d.tr * kTile, c0 = d.tc * kTile;
+  const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
+  for (int t = threadIdx.x; t < kTile * kTile; t += blockDim.x) {
+    const int r = t / kTile, c = t % kTile;
+    if (r >= mt || c >= nt) continue;
+    double s = 0.0;
+    for (int64_t g = s0; g < s1; ++g) s += part[g * (kTile * kTile) + t];
+    int64_t rel;
+    switch (mo) {  // element (r0 + r, c0 + c) of the M x N output block
+      case kRowMajor: rel = (int64_t)(r0 + r) * d.N + c0 + c; break;
+      case kColMajor: rel = (int64_t)(c0 + c) * d.M + r0 + r; break;
+      case kRowSplit: { const int q = d.qo, u = (r0 + r) / q, p = r0 + r - u * q; rel = ((int64_t)u * d.N + c0 + c) * q + p; break; }
+      default: { const int q = d.qo, u = (c0 + c) / q, p = c0 + c - u * q; rel = ((int64_t)u * d.M + r0 + r) * q + p; break; }
+    }
+    double v = alpha * s;
+    if (beta != 0.0 && cin && d.cin >= 0) v += beta * cin[d.cin + rel];
+    out[d.cout + rel] = v;
+  }
+}
+
+hipError_t launch_reduce_parts(hipStream_t s, int64_t ntiles, const int64_t* seg, const TaskDesc* desc,
+                               const double* part, double alpha, double beta, const double* cin, double* out,
+                               int32_t mo) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)ntiles), dim3(256), 0, s, seg, desc, part, alpha, beta, cin, out,
+                     mo);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------- fills
 
 __global__ void k_fill_zero(double* p, int64_t n) {

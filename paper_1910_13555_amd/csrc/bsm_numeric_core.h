@@ -117,8 +117,11 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
   // or one work item (descriptors) ahead, so that the vector memory counter
   // only ever tracks operand loads and every step issues the same number of
   // them.
+  // split-K (P.part): every work item is a unit of its own -- its sum goes
+  // to the partial buffer, and the tile's segments are added afterwards
+  const bool sk = P.part != nullptr;
   int own = e0 + r;                        // own slot of the current tile
-  while (own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
+  while (!sk && own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
   if (own >= e1) return;
   auto rec = [&](const OpPtrs& pp, const TaskDesc& d, int p, int64_t& xw, int64_t& yw)
                  __attribute__((always_inline)) {
@@ -128,7 +131,7 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
   // the item after item i (flags f): its tile's next segment, else the next
   // own slot (checked for a tile start on arrival)
   auto candidate = [&](int i, int f) __attribute__((always_inline)) {
-    return (f & kTaskLast) ? own + stride : i + 1;
+    return (sk || (f & kTaskLast)) ? own + stride : i + 1;
   };
   int it = own, ip = 0, ij = 0;
   TaskDesc id = desc_at(P, it);
@@ -253,14 +256,14 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
       pending = true;
       return;
     }
-    if (id.flags & kTaskLast) flag |= 2;   // the tile's last step: write it out
-    const bool new_tile = (id.flags & kTaskLast) != 0;
+    const bool new_tile = sk || (id.flags & kTaskLast) != 0;
+    if (new_tile) flag |= 2;               // the tile's (split-K: the item's) last step: write it out
     ip = 0;
     it = nit;
     if (it >= e1) return;
     if (new_tile) {
       own = it;
-      if (!(nd.flags & kTaskFirst)) {      // own slot inside another tile: skip ahead
+      if (!sk && !(nd.flags & kTaskFirst)) {   // own slot inside another tile: skip ahead
         while (own < e1 && !(desc_at(P, own).flags & kTaskFirst)) own += stride;
         it = own;
         if (it >= e1) return;
@@ -288,7 +291,7 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
   for (int x = 0; x < NI; ++x)
 #pragma unroll
     for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
-  auto epilogue = [&](const TaskDesc& d, const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1])
+  auto epilogue = [&](const TaskDesc& d, int item, const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1])
                       __attribute__((always_inline)) {
     const int r0 = d.tr * kTile, c0 = d.tc * kTile;
     const int mt = min(kTile, (int)d.M - r0), nt = min(kTile, (int)d.N - c0);
@@ -319,6 +322,20 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
               buf_store(ro, off, v);
             }
       }
+    } else if (sk) {  // the item's partial sum, tile-shaped (k_reduce_parts adds the segments)
+      double* pt = P.part + (int64_t)item * (kTile * kTile);
+#pragma unroll
+      for (int x = 0; x < NI; ++x)
+#pragma unroll
+        for (int y = 0; y < NJ; ++y)
+#pragma unroll
+          for (int e = 0; e < NE; ++e) {
+            const int r = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+            const int c = V == 0 ? 8 * y + 4 * ((l >> 2) & 1) + (l & 3) : 16 * y + (l & 15);
+            double av;
+            if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
+            if (r < mt && c < nt) gptr(pt)[r * kTile + c] = av;
+          }
     } else {
 #pragma unroll
       for (int x = 0; x < NI; ++x)
@@ -373,7 +390,7 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       compute(A[d], B[d], tflag[d] >> 2);
-      if (tflag[d] & 2) epilogue(desc_at(P, titem[d]), Cb[d]);
+      if (tflag[d] & 2) epilogue(desc_at(P, titem[d]), titem[d], Cb[d]);
       issue(A[d], B[d], Cb[d], titem[d], tflag[d]);
     }
   }
