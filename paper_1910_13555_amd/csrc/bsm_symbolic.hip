@@ -391,10 +391,18 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
   auto keep_of = [&](const Cand& c, int jlo) {
     return c.keep && !(P.retain && !bit_test(S.cm, c.j - jlo));
   };
+  // A row with at most 64 A entries and one column chunk (the common case):
+  // the candidates are enumerated twice instead of four times -- once for
+  // the mask of A slots hitting each output column (which gives the output
+  // columns, their product counts and every product's rank), once to place
+  // the products.  S.mask is then indexed by column.
+  const bool single = nc <= kSymChunk && P.a.ptr[row + 1] - P.a.ptr[row] <= kWave;
   for (int jlo = 0; jlo < nc; jlo += kSymChunk) {
     const int jhi = min(nc, jlo + kSymChunk);
     // 1. output columns of this chunk
     if (tid < kSymWords) { S.bm[tid] = 0u; S.cm[tid] = 0u; }
+    if (single)
+      for (int j = tid; j < kSymChunk; j += blockDim.x) S.mask[j] = 0ull;
     __syncthreads();
     if (P.cin_ptr) {
       for (int e = P.cin_ptr[row] + tid; e < P.cin_ptr[row + 1]; e += blockDim.x) {
@@ -403,9 +411,28 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
       }
     }
     __syncthreads();
-    enum_row(P, row, jlo, jhi, S.e, [&](const Cand& c) {
-      if (keep_of(c, jlo)) bit_set(S.bm, c.j - jlo);
-    });
+    if (single) {
+      const int a0 = P.a.ptr[row], a1 = P.a.ptr[row + 1];
+      if (a0 < a1) {
+        load_achunk(P, a0, a1, S.e);
+        const int total = S.e.incl[kWave - 1];
+        for (int t = tid; t < total; t += blockDim.x) {
+          const Cand c = cand_at(P, S.e, t);
+          if (keep_of(c, 0)) atomicOr((unsigned long long*)&S.mask[c.j], 1ull << c.e);
+        }
+        __syncthreads();
+      }
+      if (tid < kSymWords) {
+        uint32_t x = S.bm[tid];
+        for (int b = 0; b < 32; ++b)
+          if (S.mask[tid * 32 + b]) x |= 1u << b;
+        S.bm[tid] = x;
+      }
+    } else {
+      enum_row(P, row, jlo, jhi, S.e, [&](const Cand& c) {
+        if (keep_of(c, jlo)) bit_set(S.bm, c.j - jlo);
+      });
+    }
     // 2. word prefixes (one word per lane of the first wave)
     if (tid < kWave) {
       const uint32_t x = S.bm[tid];
@@ -450,10 +477,16 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
         tasks[S.cbase[c] + slot] = make_int2(t, tr | (tc << 16));
       });
     }
-    // 5. products per output position
-    enum_row(P, row, jlo, jhi, S.e, [&](const Cand& c) {
-      if (keep_of(c, jlo)) atomicAdd(&S.cur[rank_in(S.bm, S.wpre, c.j - jlo)], 1);
-    });
+    // 5. products per output position (single: counted from the column masks;
+    //    S.colq is complete after the barrier above)
+    if (single) {
+      for (int q = tid; q < npos; q += blockDim.x) S.cur[q] = __popcll(S.mask[S.colq[q] - jlo]);
+      __syncthreads();
+    } else {
+      enum_row(P, row, jlo, jhi, S.e, [&](const Cand& c) {
+        if (keep_of(c, jlo)) atomicAdd(&S.cur[rank_in(S.bm, S.wpre, c.j - jlo)], 1);
+      });
+    }
     // 6. positions' product offsets
     if (tid < kWave) {
       int64_t carry = 0;
@@ -472,7 +505,22 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_fill(SymParams P, const int
     __syncthreads();
     // 7. place products, A chunk by A chunk, ranked by A slot
     const int a0 = P.a.ptr[row], a1 = P.a.ptr[row + 1];
-    for (int ab = a0; ab < a1; ab += kWave) {
+    if (single && a0 < a1) {  // the chunk is still loaded, the masks are per column
+      const int total = S.e.incl[kWave - 1];
+      for (int t = tid; t < total; t += blockDim.x) {
+        const Cand c = cand_at(P, S.e, t);
+        if (!keep_of(c, 0)) continue;
+        const int q = rank_in(S.bm, S.wpre, c.j);
+        const int rank = __popcll(S.mask[c.j] & ((1ull << c.e) - 1ull));
+        const int64_t g = rowprod0 + S.cur[q] + rank;
+        const int ap = S.e.apos[c.e];
+        px[g] = P.a.off[P.a.blk ? P.a.blk[ap] : ap] | ((int64_t)P.ks[c.k] << 48);
+        py[g] = P.b.off[P.b.blk ? P.b.blk[c.bp] : c.bp];
+        if (pblk) pblk[g] = (int32_t)(rowblk0 + q);
+      }
+      __syncthreads();
+    }
+    for (int ab = single ? a1 : a0; ab < a1; ab += kWave) {
       load_achunk(P, ab, a1, S.e);
       const int total = S.e.incl[kWave - 1];
       for (int q = tid; q < npos; q += blockDim.x) S.mask[q] = 0ull;

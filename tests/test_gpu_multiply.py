@@ -207,3 +207,35 @@ def test_work_order_panels_bit_identical(bsm):
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     check_against_oracle(bsm, d["A"], d["B"], eps=d["eps"])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plan_stacks_match_oracle(bsm, seed):
+    """The symbolic phase alone (no numeric launch): output pattern and every
+    product of the stacks against the oracle, for rows of at most 64 A
+    entries (two candidate passes) and longer rows (chunked passes), with
+    C_in, filtering and retained sparsity."""
+    rng = np.random.default_rng(5000 + seed)
+    nbk = [20, 150][seed % 2]                  # A entries per row: <= 64, or > 64
+    sizes = rng.choice(np.array([1, 5, 13], np.int32), size=max(nbk, 40))
+    rs, ks, cs = sizes[:7], sizes[:nbk], sizes[:30]
+    dA = workloads.random_matrix(rng, rs, ks, 0.8)
+    dB = workloads.random_matrix(rng, ks, cs, 0.3)
+    dC = workloads.random_matrix(rng, rs, cs, 0.2) if seed % 3 else None
+    oA, oB = ob.BlockSparse.from_workload(dA), ob.BlockSparse.from_workload(dB)
+    oC = ob.BlockSparse.from_workload(dC) if dC is not None else None
+    eps = 0.0
+    if seed >= 2:
+        na, nb = sorted(ob.norms(oA).values()), sorted(ob.norms(oB).values())
+        eps = math.sqrt(na[len(na) // 2] * nb[len(nb) // 2])
+    retain = seed == 5 and dC is not None
+    A = bsm.BlockSparseMatrix.from_workload(dA)
+    B = bsm.BlockSparseMatrix.from_workload(dB)
+    Cm = bsm.BlockSparseMatrix.from_workload(dC) if dC is not None else None
+    plan = bsm.bsm_multiply_plan(A.pattern.ctx, A.pattern, A.values, B.pattern, B.values,
+                                 Cm.pattern if Cm else None, eps, retain_sparsity=retain)
+    ref, trip = ob.multiply(oA, oB, oC, 1.0, 0.0, eps, False, False, retain)
+    pat = plan.c_pattern()
+    rows, cols, _ = pat.export()
+    assert sorted(zip(rows.tolist(), cols.tolist())) == sorted(ref.blocks)
+    assert stack_triples(plan, A, B, False, False, pat) == sorted(trip)
