@@ -139,10 +139,12 @@ bsm_status bsm_block_norms(bsm_ctx ctx, bsm_pattern p, const double* vals, doubl
  * only precision is double, Sec. 3): each operand value is rounded to float32
  * (nearest even) and cut into bfloat16 pieces (nearest even; the remainders
  * are exact in float32); block products become sums of piece products on the
- * bfloat16 matrix cores, summed in float32 over chunks of 32 concatenated k
- * and each chunk added into float64.  Norms, the filter, alpha, beta, C_in
- * and C_out stay float64.  Split plans need trans_a = trans_b = 0
- * (BSM_E_UNSUPPORTED otherwise) and have no gradient. */
+ * bfloat16 matrix cores, summed in float32 over each output tile's whole
+ * product run and added into float64 once.  Norms, the filter, alpha, beta,
+ * C_in and C_out stay float64.  Split plans need trans_a = trans_b = 0 and
+ * operands of at most 2^30 / pieces values with their block rows padded to a
+ * multiple of 8 (BSM_E_UNSUPPORTED otherwise), and have no gradient; each
+ * execute splits both operands into library-owned piece arrays first. */
 typedef struct bsm_mm_opts {
   int32_t trans_a;
   int32_t trans_b;
@@ -207,7 +209,12 @@ bsm_status bsm_multiply(bsm_ctx ctx, double alpha, bsm_pattern A, const double* 
  * the stored layout of A / B, overwritten (blocks without products get 0);
  * either may be NULL to skip it.  The first call builds, per operand, one
  * product list per block of that operand (same norm test, same output
- * pattern) and keeps them with the plan.  FP64 plans only. */
+ * pattern) and keeps them with the plan.  A gradient whose output tiles hold
+ * many products on average (e.g. a small operand against a long one) is
+ * computed split-K: its product lists are cut into segments run in parallel,
+ * and each tile's segment sums are added in segment order (deterministic;
+ * scratch of 8 KB per segment, at most 8 GB, allocated from the context).
+ * FP64 plans only. */
 bsm_status bsm_plan_backward(bsm_plan plan, double alpha, const double* dc_vals,
                              const double* a_vals, const double* b_vals, double* da_vals,
                              double* db_vals);
@@ -263,7 +270,9 @@ bsm_status bsm_tpattern_destroy(bsm_tpattern t);
  * T2 rows = the summed modes, columns = its free modes in output order.  The
  * block index map is computed from the tensor indices.  Layouts that already
  * match the matricization (row-major, transposed, or the summed modes
- * between two groups of free modes) are read and written in place; others
+ * between two groups of free modes) are read and written in place, except a
+ * first operand of the last kind when the rest allows the row-major kernels:
+ * it is permuted to row-major at execute (one pass over it).  Other layouts
  * are permuted by the remap kernel into scratch buffers at execute.
  * T3_in: optional output pattern (NULL = empty).  The resulting plan is used
  * with bsm_plan_execute / bsm_plan_backward / bsm_plan_info with tensor value

@@ -1,15 +1,20 @@
 // Numeric phase of the block-sparse multiply (gfx950 / CDNA4).
 //
-// Work item ("task"): one output tile -- at most 32 x 32 elements of one
-// output block C_ij -- with one segment of at most 64 of that block's
-// products (its stack, Sec. 2), accumulated in registers:
+// Work item: one output tile -- at most 32 x 32 elements of one output block
+// C_ij -- accumulated in registers:
 //     C_ij(tile) = beta * C_in + alpha * sum_k A_ik(tile rows) . B_kj(tile cols).
+// Row-major plans (run_steps): one item per tile, its products expanded into
+// step records (bsm_steps.hip).  Other layouts (run_tiles): items of at most
+// 64 of the block's products (its stack, Sec. 2); a tile with more has
+// several items, run by one wavefront in order, or -- split-K, for gradients
+// of few long tiles -- by different wavefronts whose partial sums are added
+// afterwards in item order.
 //
 // Operands go straight from memory into matrix-core operand registers: each
 // lane loads exactly the A and B elements its lane slot of the instruction
-// needs, with no LDS staging, no tables and no barriers.  A "step" is one
-// product's k range [16 j, 16 j + 16): four instruction k-steps of 4 (steps
-// past the product's K are skipped).  Two instruction shapes:
+// needs, with no LDS staging and no barriers.  A "step" is one product's k
+// range [16 j, 16 j + 16): four instruction k-steps of 4 (k-steps past the
+// product's K are skipped).  Two instruction shapes:
 //   variant 0: FP64 4x4x4 in its 4-block form -- an 8 x 8 output per
 //              instruction, tiles padded to multiples of 8;
 //   variant 1: FP64 16x16x4 -- a 16 x 16 output per instruction, tiles padded
@@ -17,13 +22,13 @@
 // The variant of each tile class (padded rows x columns in {8,16,24,32}^2)
 // comes from the tuning table.
 //
-// The kernels are persistent: wavefronts own contiguous slices of one
-// class's tasks (contiguous per XCD too, so output blocks that share operand
-// blocks are served from one L2), and run them as one software pipeline of
+// The kernels are persistent: each XCD owns a contiguous share of a class's
+// items (an eighth of its steps on the row-major path), so output blocks
+// that share operand blocks are served from one L2, and its wavefronts take
+// the share's tiles cyclically, running them as one software pipeline of
 // depth D: the loads of step s + D are issued as soon as step s has been
-// multiplied, across task boundaries, and each task's product records are
-// fetched one task ahead.  Unused operand slots read a zero in device memory,
-// so every step issues the same number of loads.
+// multiplied, across tile boundaries.  Unused operand slots read zero, so
+// every step issues the same number of loads.
 //
 // Every output element has exactly one owner: no atomics, and results are
 // bit-identical from run to run (the GPU counterpart of Sec. 2's static
