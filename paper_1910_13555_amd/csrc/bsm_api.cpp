@@ -336,7 +336,8 @@ void build_grad_lists(bsm_plan pl, int which) {
   const int64_t ng = G->nblk;
   std::vector<int32_t> g_row(ng), g_col(ng);
   std::vector<int64_t> g_off(ng);
-  std::vector<int2> by_class[kClasses];
+  // tiles grouped by class, blocks in order within a class: count, then place
+  int64_t cnt[kClasses + 1] = {};
   for (int32_t r = 0; r < gnr; ++r)
     for (int32_t e = gptr[r]; e < gptr[r + 1]; ++e) {
       g_row[e] = r;
@@ -344,17 +345,20 @@ void build_grad_lists(bsm_plan pl, int which) {
       g_off[e] = G->h_off[gt ? G->h_tblk[e] : G->stored(e)];
       for_tiles_host(grs[r], gcs[gcol[e]], [&](int tr, int tc) {
         const int m = std::min(kTile, grs[r] - tr * kTile), n = std::min(kTile, gcs[gcol[e]] - tc * kTile);
-        by_class[tile_class(m, n)].push_back(make_int2(e, tr | (tc << 16)));
+        cnt[tile_class(m, n) + 1]++;
       });
     }
-  std::vector<int2> tasks;
-  L.cls_tile[0] = 0;
-  for (int c = 0; c < kClasses; ++c) {
-    tasks.insert(tasks.end(), by_class[c].begin(), by_class[c].end());
-    L.cls_tile[c + 1] = (int32_t)tasks.size();
-  }
-  const int64_t nt = (int64_t)tasks.size();
+  for (int c = 0; c < kClasses; ++c) cnt[c + 1] += cnt[c];
+  const int64_t nt = cnt[kClasses];
   if (nt >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 gradient tiles");
+  for (int c = 0; c <= kClasses; ++c) L.cls_tile[c] = (int32_t)cnt[c];
+  std::vector<int2> tasks(nt);
+  for (int32_t r = 0; r < gnr; ++r)
+    for (int32_t e = gptr[r]; e < gptr[r + 1]; ++e)
+      for_tiles_host(grs[r], gcs[gcol[e]], [&](int tr, int tc) {
+        const int m = std::min(kTile, grs[r] - tr * kTile), n = std::min(kTile, gcs[gcol[e]] - tc * kTile);
+        tasks[cnt[tile_class(m, n)]++] = make_int2(e, tr | (tc << 16));
+      });
   L.g_row = make_dev(ctx, g_row);
   L.g_col = make_dev(ctx, g_col);
   L.g_off = make_dev(ctx, g_off);

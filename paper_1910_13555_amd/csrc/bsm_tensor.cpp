@@ -14,6 +14,7 @@
 // scratch buffer (the paper's conversion step, avoided when the caller picks
 // a compatible layout).
 #include <array>
+#include <functional>
 #include <string>
 
 #include "bsm_host.h"
@@ -29,6 +30,16 @@ struct bsm_tpattern_s {
   int64_t nblocks = 0, nvals = 0;
   std::vector<int32_t> idx;               // nblocks x rank, in packing order
   std::vector<int64_t> off;               // nblocks + 1
+  // A contraction's output pattern keeps its blocks' matrix row and column
+  // numbers on the device and fills idx and off on first use (export or a
+  // later contraction), so that producing it costs no host pass.
+  std::function<void(bsm_tpattern_s&)> pending;
+  void ensure() {
+    if (!pending) return;
+    auto f = std::move(pending);
+    pending = nullptr;
+    f(*this);
+  }
   int32_t bsize(int64_t b, int m) const { return sz[m][idx[b * rank + m]]; }
 };
 
@@ -203,9 +214,19 @@ struct TupleIndex {
   }
 };
 
-Key sub_key(const bsm_tpattern_s& t, const std::string& spec, const std::string& modes, int64_t b) {
+// Positions in a tensor's index list of a group of its modes.
+struct ModeSel {
+  int n = 0;
+  int pos[4] = {0, 0, 0, 0};
+  ModeSel(const std::string& spec, const std::string& modes) : n((int)modes.size()) {
+    for (int a = 0; a < n; ++a) pos[a] = (int)spec.find(modes[a]);
+  }
+};
+
+Key sub_key(const bsm_tpattern_s& t, const ModeSel& sel, int64_t b) {
   Key k = {0, 0, 0, 0};
-  for (size_t a = 0; a < modes.size(); ++a) k[a] = t.idx[b * t.rank + spec.find(modes[a])];
+  const int32_t* ix = t.idx.data() + b * t.rank;
+  for (int a = 0; a < sel.n; ++a) k[a] = ix[sel.pos[a]];
   return k;
 }
 
@@ -322,6 +343,9 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
                             bsm_tpattern T2, const double* t2_vals, bsm_tpattern T3,
                             double eps, const bsm_mm_opts& o) {
   if (!T1 || !T2) fail(BSM_E_INVALID, "NULL tensor pattern");
+  T1->ensure();
+  T2->ensure();
+  if (T3) T3->ensure();
   if (T1->ctx != ctx || T2->ctx != ctx || (T3 && T3->ctx != ctx)) fail(BSM_E_INVALID, "pattern of another context");
   if (!(eps >= 0.0) || !std::isfinite(eps)) fail(BSM_E_INVALID, "filter_eps must be finite and >= 0");
   if (o.trans_a || o.trans_b) fail(BSM_E_INVALID, "transposition is expressed through the spec");
@@ -367,8 +391,10 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
     if (space <= (int64_t(1) << 24)) {  // dense table (at most 64 MB)
       ti.table.assign(space, -1);
       for (const Src& s : srcs)
-        if (s.first)
-          for (int64_t b = 0; b < s.first->nblocks; ++b) ti.table[ti.lin(sub_key(*s.first, *s.second, modes, b))] = 0;
+        if (s.first) {
+          const ModeSel sel(*s.second, modes);
+          for (int64_t b = 0; b < s.first->nblocks; ++b) ti.table[ti.lin(sub_key(*s.first, sel, b))] = 0;
+        }
       int32_t n = 0;
       for (int64_t v = 0; v < space; ++v) {
         if (ti.table[v] < 0) continue;
@@ -383,8 +409,10 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
       }
     } else {
       for (const Src& s : srcs)
-        if (s.first)
-          for (int64_t b = 0; b < s.first->nblocks; ++b) ti.keys.push_back(sub_key(*s.first, *s.second, modes, b));
+        if (s.first) {
+          const ModeSel sel(*s.second, modes);
+          for (int64_t b = 0; b < s.first->nblocks; ++b) ti.keys.push_back(sub_key(*s.first, sel, b));
+        }
       std::sort(ti.keys.begin(), ti.keys.end());
       ti.keys.erase(std::unique(ti.keys.begin(), ti.keys.end()), ti.keys.end());
       ti.dims.clear();
@@ -408,15 +436,19 @@ bsm_plan make_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, cons
   std::vector<std::array<int32_t, 3>> e1, e2, e3;
   e1.reserve(T1->nblocks);
   e2.reserve(T2->nblocks);
-  for (int64_t b = 0; b < T1->nblocks; ++b)
-    e1.push_back({ext->rows.id(sub_key(*T1, sp.s1, sp.free1, b)), kidx.id(sub_key(*T1, sp.s1, sp.con, b)), (int32_t)b});
-  for (int64_t b = 0; b < T2->nblocks; ++b)
-    e2.push_back({kidx.id(sub_key(*T2, sp.s2, sp.con, b)), ext->cols.id(sub_key(*T2, sp.s2, sp.free2, b)), (int32_t)b});
+  {
+    const ModeSel r1(sp.s1, sp.free1), k1(sp.s1, sp.con), k2(sp.s2, sp.con), c2(sp.s2, sp.free2);
+    for (int64_t b = 0; b < T1->nblocks; ++b)
+      e1.push_back({ext->rows.id(sub_key(*T1, r1, b)), kidx.id(sub_key(*T1, k1, b)), (int32_t)b});
+    for (int64_t b = 0; b < T2->nblocks; ++b)
+      e2.push_back({kidx.id(sub_key(*T2, k2, b)), ext->cols.id(sub_key(*T2, c2, b)), (int32_t)b});
+  }
   ext->M1 = build_matrix(ctx, rsz, ksz, e1, T1->off, T1->nvals);
   ext->M2 = build_matrix(ctx, ksz, csz, e2, T2->off, T2->nvals);
   if (T3) {
+    const ModeSel r3(sp.out, sp.free1), c3(sp.out, sp.free2);
     for (int64_t b = 0; b < T3->nblocks; ++b)
-      e3.push_back({ext->rows.id(sub_key(*T3, sp.out, sp.free1, b)), ext->cols.id(sub_key(*T3, sp.out, sp.free2, b)), (int32_t)b});
+      e3.push_back({ext->rows.id(sub_key(*T3, r3, b)), ext->cols.id(sub_key(*T3, c3, b)), (int32_t)b});
     ext->M3 = build_matrix(ctx, rsz, csz, e3, T3->off, T3->nvals);
   }
   // remaps of operands whose layout does not fit
@@ -488,9 +520,6 @@ bsm_tpattern output_tpattern(bsm_plan pl) {
   if (!ext) fail(BSM_E_INVALID, "not a contraction plan");
   bsm_ctx ctx = pl->ctx;
   const Spec& sp = ext->sp;
-  const auto crow = download(ctx, pl->c_row.p, pl->c_nblk);
-  const auto ccol = download(ctx, pl->c_col.p, pl->c_nblk);
-  const auto coff = download(ctx, pl->c_off.p, pl->c_nblk + 1);
   auto t = std::make_unique<bsm_tpattern_s>();
   t->ctx = ctx;
   t->rank = (int32_t)sp.out.size();
@@ -498,15 +527,45 @@ bsm_tpattern output_tpattern(bsm_plan pl) {
   t->sz = ext->out_sz;
   t->nblocks = pl->c_nblk;
   t->nvals = pl->c_nvals;
-  t->off = coff;
-  t->idx.resize(pl->c_nblk * t->rank);
-  for (int64_t b = 0; b < pl->c_nblk; ++b)
-    for (int m = 0; m < t->rank; ++m) {
-      const char c = sp.out[m];
-      const size_t a1 = sp.free1.find(c);
-      t->idx[b * t->rank + m] = a1 != std::string::npos ? ext->rows.keys[crow[b]][a1]
-                                                        : ext->cols.keys[ccol[b]][sp.free2.find(c)];
+  // the pattern owns copies of the plan's output numbering (the plan may go first)
+  struct Src {
+    DBuf<int32_t> row, col;
+    DBuf<int64_t> off;
+    std::vector<Key> rk, ck;
+    int side[4] = {0, 0, 0, 0}, pos[4] = {0, 0, 0, 0};
+  };
+  auto src = std::make_shared<Src>();
+  const int64_t n = pl->c_nblk;
+  src->row = DBuf<int32_t>(ctx, n);
+  src->col = DBuf<int32_t>(ctx, n);
+  src->off = DBuf<int64_t>(ctx, n + 1);
+  if (n > 0) {
+    hip_check(hipMemcpyAsync(src->row.p, pl->c_row.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream),
+              "copy");
+    hip_check(hipMemcpyAsync(src->col.p, pl->c_col.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream),
+              "copy");
+  }
+  hip_check(hipMemcpyAsync(src->off.p, pl->c_off.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, ctx->stream),
+            "copy");
+  src->rk = ext->rows.keys;
+  src->ck = ext->cols.keys;
+  for (int m = 0; m < t->rank; ++m) {
+    const size_t a1 = sp.free1.find(sp.out[m]);
+    src->side[m] = a1 == std::string::npos;
+    src->pos[m] = (int)(a1 != std::string::npos ? a1 : sp.free2.find(sp.out[m]));
+  }
+  t->pending = [src](bsm_tpattern_s& t) {
+    set_device(t.ctx);
+    const auto crow = download(t.ctx, src->row.p, t.nblocks);
+    const auto ccol = download(t.ctx, src->col.p, t.nblocks);
+    t.off = download(t.ctx, src->off.p, t.nblocks + 1);
+    t.idx.resize(t.nblocks * t.rank);
+    for (int64_t b = 0; b < t.nblocks; ++b) {
+      const Key& r = src->rk[crow[b]];
+      const Key& c = src->ck[ccol[b]];
+      for (int m = 0; m < t.rank; ++m) t.idx[b * t.rank + m] = src->side[m] ? c[src->pos[m]] : r[src->pos[m]];
     }
+  };
   return t.release();
 }
 
@@ -535,6 +594,7 @@ bsm_status bsm_tpattern_info(bsm_tpattern t, int32_t* rank, int64_t* nblocks, in
 bsm_status bsm_tpattern_export(bsm_tpattern t, int32_t* blk_idx, int64_t* blk_off) {
   return guard([&] {
     if (!t) fail(BSM_E_INVALID, "NULL tensor pattern");
+    t->ensure();
     if (blk_idx) std::copy(t->idx.begin(), t->idx.end(), blk_idx);
     if (blk_off) std::copy(t->off.begin(), t->off.end() - 1, blk_off);
   });

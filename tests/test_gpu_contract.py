@@ -173,3 +173,30 @@ def test_contract_large_tuple_space(bsm):
     ref, pairs = ot.contract(to_ref(d1), to_ref(d2), "abc,cd->abd")
     assert R.plan.info["nprod"] == len(pairs)
     assert_tensor_close(tensor_to_oracle(R.pattern, R.values, ref.mode_sizes), ref, TOL)
+
+
+def test_chained_output_pattern(bsm):
+    """An output pattern feeds a second contraction after its plan is gone:
+    the pattern's block list is materialised from its own copy of the plan's
+    output numbering."""
+    import gc
+    rng = np.random.default_rng(4242)
+    nb = {c: int(rng.integers(2, 5)) for c in "abcde"}
+    sz = {c: rng.choice([1, 2, 3, 5], size=nb[c]).astype(np.int32) for c in "abcde"}
+    d1 = workloads.random_tensor(rng, [sz[c] for c in "abc"], 0.5)
+    d2 = workloads.random_tensor(rng, [sz[c] for c in "cd"], 0.6)
+    d3 = workloads.random_tensor(rng, [sz[c] for c in "de"], 0.6)
+    R1 = bsm.contract("abc,cd->abd", to_lib(bsm, d1), to_lib(bsm, d2))
+    R1.plan = None
+    gc.collect()
+    R2 = bsm.contract("abd,de->abe", R1, to_lib(bsm, d3))
+    torch.cuda.synchronize()
+    ref1, _ = ot.contract(to_ref(d1), to_ref(d2), "abc,cd->abd")
+    ref2, pairs = ot.contract(ref1, to_ref(d3), "abd,de->abe")
+    assert R2.plan.info["nprod"] == len(pairs)
+    got1 = tensor_to_oracle(R1.pattern, R1.values, ref1.mode_sizes)
+    assert sorted(got1.blocks) == sorted(ref1.blocks)
+    got2 = tensor_to_oracle(R2.pattern, R2.values, ref2.mode_sizes)
+    assert sorted(got2.blocks) == sorted(ref2.blocks)
+    if ref2.blocks:
+        assert_tensor_close(got2, ref2, TOL)
