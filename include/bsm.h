@@ -172,7 +172,9 @@ typedef struct bsm_plan_info_t {
  * device, optional precomputed bsm_block_norms output.  C_in: optional
  * pattern (NULL = empty).  filter_eps: finite, >= 0.
  * Sizes: op(A) column sizes must equal op(B) row sizes; C_in's sizes must
- * match op(A) rows and op(B) columns (BSM_E_SHAPE).  Synchronises once to
+ * match op(A) rows and op(B) columns (BSM_E_SHAPE).  The largest row size
+ * times the largest column size of op(A), op(B) and C must stay below 2^28
+ * values (blocks under 2 GB; BSM_E_UNSUPPORTED otherwise).  Synchronises once to
  * learn the output size.  The plan keeps references to A, B and C_in: they
  * must outlive it. */
 bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals,

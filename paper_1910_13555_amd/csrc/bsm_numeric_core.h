@@ -42,9 +42,6 @@ namespace bsm {
 // Tuning table: the variant of each tile class (bsm_numeric.hip).
 extern int32_t g_variant[kClasses];
 
-// Target of the loads of padding slots (see above).
-static __device__ double kZeroD = 0.0;
-
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -76,6 +73,48 @@ __device__ __forceinline__ f64x2 buf_load2(__amdgpu_buffer_rsrc_t r, uint32_t of
 // and (2, 3) are adjacent pairs (one 16-byte load each), and k-steps 0-1
 // still cover k < 8, so steps with at most 8 valid k skip k-steps 2-3.
 __host__ __device__ constexpr int step_k(int ks, int lk) { return 8 * (ks >> 1) + 2 * lk + (ks & 1); }
+
+// Generic layouts: element offsets, inside its block, of the operand values a
+// lane reads in the four k-steps of a step: k, k + 4, k + 8, k + 12 along
+// the summed dimension, at index i of the other one (a row of the first
+// operand when xside, else a column of the second).  e is the block's extent
+// along i, K along k, q the split factor of a split mode.
+__device__ __forceinline__ void gen_offsets(int mode, bool xside, int i, int k, int e, int K, int q,
+                                            uint32_t (&o)[4]) {
+  // the mode's view as (i, k): linear in k, or k split as k = u q + p
+  // (a split factor is at least 1; the guard keeps the loop below bounded)
+  const int qs = q > 0 ? q : 1;
+  int base = 0, step = 0;
+  bool ksplit = false;
+  int S = 0;  // for a split k: offset (u S + i) q + p
+  if (xside) {             // X(i, k): e rows, K columns
+    switch (mode) {
+      case kRowMajor: base = i * K + k; step = 4; break;
+      case kColMajor: base = k * e + i; step = 4 * e; break;
+      case kRowSplit: { const int u = i / qs, p = i - u * qs; base = (u * K + k) * qs + p; step = 4 * qs; break; }
+      default: ksplit = true; S = e; break;
+    }
+  } else {                 // Y(k, i): K rows, e columns
+    switch (mode) {
+      case kRowMajor: base = k * e + i; step = 4 * e; break;
+      case kColMajor: base = i * K + k; step = 4; break;
+      case kRowSplit: ksplit = true; S = e; break;
+      default: { const int u = i / qs, p = i - u * qs; base = (u * K + k) * qs + p; step = 4 * qs; break; }
+    }
+  }
+  if (!ksplit) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o[t] = (uint32_t)(base + t * step);
+    return;
+  }
+  int u = k / qs, p = k - u * qs;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    o[t] = (uint32_t)((u * S + i) * qs + p);
+    p += 4;
+    while (p >= qs) { p -= qs; ++u; }   // at most 4 passes
+  }
+}
 
 // Kernels: (variant, tile size) combinations, each with its own pipeline
 // depth and register budget (resident wavefronts per SIMD).
@@ -179,28 +218,29 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
     const int r0 = id.tr * kTile, c0 = id.tc * kTile;
     const int mt = min(kTile, (int)id.M - r0), nt = min(kTile, (int)id.N - c0);
     if constexpr (GEN) {
+      // Any layout, through buffer resources over the product's two blocks:
+      // each lane's four k offsets of a step follow from one base and one
+      // stride, except where k is the split mode (then stepped across the
+      // split); lanes outside the tile or the valid k read offset kOob.
       const int qa = P.mx == kRowSplit ? (int)id.qo : q;
+      const auto ra = make_rsrc(has ? ipp.X + xo : nullptr, has ? (uint32_t)(id.M * K) * 8u : 0u);
+      const auto rb = make_rsrc(has ? ipp.Y + yo : nullptr, has ? (uint32_t)(K * id.N) * 8u : 0u);
+      const int kl = k0 + lk;
 #pragma unroll
       for (int x = 0; x < NI; ++x) {
         const int r = TI * x + lrA;
+        uint32_t o[4];
+        gen_offsets(P.mx, true, r0 + r, kl, (int)id.M, K, qa, o);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int kq = 4 * ks + lk;
-          const bool v = r < mt && kq < kv;
-          const int64_t ad = eaddr(P.mx, xo, r0 + r, k0 + kq, id.M, K, qa);
-          a[x][ks] = *(v ? gptr(ipp.X) + ad : gptr(&kZeroD));
-        }
+        for (int ks = 0; ks < 4; ++ks) a[x][ks] = buf_load(ra, (r < mt && 4 * ks + lk < kv) ? 8u * o[ks] : kOob);
       }
 #pragma unroll
       for (int y = 0; y < NJ; ++y) {
         const int c = TI * y + lcB;
+        uint32_t o[4];
+        gen_offsets(P.my, false, c0 + c, kl, (int)id.N, K, q, o);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int kq = 4 * ks + lk;
-          const bool v = c < nt && kq < kv;
-          const int64_t ad = eaddr(P.my, yo, k0 + kq, c0 + c, K, id.N, q);
-          b[y][ks] = *(v ? gptr(ipp.Y) + ad : gptr(&kZeroD));
-        }
+        for (int ks = 0; ks < 4; ++ks) b[y][ks] = buf_load(rb, (c < nt && 4 * ks + lk < kv) ? 8u * o[ks] : kOob);
       }
     } else {
       // Row-major blocks through buffer resources spanning exactly the
