@@ -450,7 +450,12 @@ def main():
         res["batched"] = batched_section(bsm, max(2, args.steps // 4), stream)
         res["tall_skinny"] = tall_skinny_section(bsm, max(2, args.steps // 4), stream)
     if args.rank3:
+        tuned = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "rank3.json")
+        if os.path.exists(tuned):
+            bsm.bsm_tune_load(tuned)      # the autotuner's table for this workload
         res["rank3"] = rank3_section(bsm, 3, stream)
+        res["rank3"]["tuning"] = bsm.bsm_tune_get()
+        bsm.bsm_tune_load(TUNED)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(res), flush=True)

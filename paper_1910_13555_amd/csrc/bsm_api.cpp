@@ -82,6 +82,13 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     P.cin_ptr = C->d_ptr.p;
     P.cin_col = C->d_col.p;
     P.cin_off = C->d_off.p;
+    C->ensure_host();
+    if (!C->h_blk.empty()) {  // blocks stored out of canonical order (a contraction's T3): offsets per entry
+      std::vector<int64_t> o(C->nblk);
+      for (int64_t e = 0; e < C->nblk; ++e) o[e] = C->h_off[C->stored(e)];
+      pl->cin_canon = make_dev(ctx, o);
+      P.cin_off = pl->cin_canon.p;
+    }
   }
   if (P.eps2 > 0.0) {  // the plan keeps its own norms: the gradient reuses the same test
     pl->na = DBuf<double>(ctx, A->nblk);
@@ -143,7 +150,8 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                             pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p,
                             pl->step_path() ? pblk.p : nullptr),
             "symbolic fill");
-  pl->c_same_as_cin = C && pl->c_nblk == C->nblk;
+  // in place only where C_out's packing is C_in's (same blocks, canonical order)
+  pl->c_same_as_cin = C && pl->c_nblk == C->nblk && C->h_blk.empty();
   if (g_panel[0] > 0 && pl->ntasks > 1) {
     const int64_t sb = panel_order_scratch_bytes(pl->ntasks);
     DBuf<char> sc(ctx, sb);
@@ -453,6 +461,7 @@ void execute_grad(bsm_plan pl, int which, double alpha, const double* x, const d
   P.seg = L.seg.p;
   std::copy(L.cls_tile, L.cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
+  attach_side_streams(pl->ctx, P);
   // split-K when the tiles hold many segments on average (few output tiles,
   // long product lists: e.g. the gradient of a small operand)
   const int64_t segs = (L.nprod + 63) / 64;          // segments of at most 64 products

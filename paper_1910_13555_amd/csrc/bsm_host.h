@@ -421,6 +421,7 @@ struct bsm_plan_s {
   const int32_t* c_rs = nullptr;  // output block sizes: the operands' device size vectors
   const int32_t* c_cs = nullptr;
   DBuf<int64_t> c_off, cin_off, pptr, px, py;
+  DBuf<int64_t> cin_canon;   // C_in block offsets by canonical entry, when C_in stores its blocks out of order
   DBuf<int2> tasks;   // output tiles, sorted by tile class
   int64_t ntasks = 0; // tiles
   int32_t cls_tile[kClasses + 1] = {0};  // class c's tiles: [cls_tile[c], cls_tile[c+1])

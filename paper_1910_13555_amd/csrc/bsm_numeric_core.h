@@ -452,7 +452,11 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
 // records off the vector memory path, whose address unit bounds these
 // kernels); tile descriptors come through scalar loads one tile ahead, and
 // the fields the epilogue needs travel with the step.
-template <int V, int NI, int NJ, bool CIN, bool BATCH, int D>
+// TR: the operands enter the matrix-core instructions swapped, so each
+// accumulates the transposed tile and a lane's values lie along the rows of
+// the output -- used for outputs in split rows, whose consecutive rows are
+// adjacent in memory (columns otherwise).
+template <int V, int NI, int NJ, bool CIN, bool BATCH, int D, bool TR>
 __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, int r, int stride) {
   const int l = threadIdx.x;
   const int lrA = V == 0 ? 4 * ((l >> 3) & 1) + (l & 3) : (l & 15);   // row inside an instruction tile
@@ -507,8 +511,18 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   // only a column that is never stored).  16x16x4: tiles 32 wide; 4x4x4:
   // every two 8-column tiles.
   constexpr int NPAIR = V == 1 ? (NJ == 2 ? 1 : 0) : NJ / 2;
-  auto bcol = [&](int y) __attribute__((always_inline)) {   // tile column of this lane in instruction tile y
-    return y < 2 * NPAIR ? 2 * TI * (y >> 1) + 2 * lcB + (y & 1) : TI * y + lcB;
+  auto colmap = [&](int y, int i) __attribute__((always_inline)) {   // tile column of column i of instruction tile y
+    return y < 2 * NPAIR ? 2 * TI * (y >> 1) + 2 * i + (y & 1) : TI * y + i;
+  };
+  auto bcol = [&](int y) __attribute__((always_inline)) { return colmap(y, lcB); };   // this lane's B column
+  // tile row / column of accumulator value e of instruction tile (x, y) in this lane
+  auto orow = [&](int x, int e) __attribute__((always_inline)) {
+    if constexpr (TR) return TI * x + lrA;
+    else return V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
+  };
+  auto ocol = [&](int y, int e) __attribute__((always_inline)) {
+    if constexpr (TR) return colmap(y, V == 0 ? 4 * ((l >> 2) & 1) + (l >> 4) : 4 * e + (l >> 4));
+    else return bcol(y);
   };
   uint32_t offB[NJ][4];
   int rowA[NI];
@@ -545,7 +559,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   int tflag[D], tpid[D], tmn[D], ttile[D], tq[D];
   // output element (r, c) of an M x N block: row-major, or split rows
   // (r = u q + p stored at (u N + c) q + p; the tile's q travels with it)
-  const bool osplit = P.mo == kRowSplit;
+  constexpr bool osplit = TR;   // dispatched on P.mo == kRowSplit
   auto oel = [&](int r, int c, int N, int q) __attribute__((always_inline)) {
     if (!osplit) return r * N + c;
     const int u = r / q;
@@ -609,8 +623,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
         for (int y = 0; y < NJ; ++y)
 #pragma unroll
           for (int e = 0; e < NE; ++e) {
-            const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
-            const int cc = bcol(y);
+            const int rr = orow(x, e), cc = ocol(y, e);
             const uint32_t off = (rr < mt && cc < nt) ? (uint32_t)oel(r0 + rr, c0 + cc, id.N, id.qo) * 8u : kOob;
             cb[x][y][e] = buf_load(rc, off);
           }
@@ -655,8 +668,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
         for (int y = 0; y < NJ; ++y)
 #pragma unroll
           for (int e = 0; e < NE; ++e) {
-            const int rr = V == 0 ? 8 * x + 4 * ((l >> 3) & 1) + (l >> 4) : 16 * x + 4 * e + (l >> 4);
-            const int cc = bcol(y);
+            const int rr = orow(x, e), cc = ocol(y, e);
             double av;
             if constexpr (V == 0) av = acc[x][y]; else av = acc[x][y][e];
             // branch-free: lanes outside the tile get an offset past the block
@@ -682,8 +694,12 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
         for (int x = 0; x < NI; ++x)
 #pragma unroll
           for (int y = 0; y < NJ; ++y) {
-            if constexpr (V == 0)
+            if constexpr (V == 0 && TR)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(b[y][ks], a[x][ks], acc[x][y], 0, 0, 0);
+            else if constexpr (V == 0)
               acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
+            else if constexpr (TR)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[y][ks], a[x][ks], acc[x][y], 0, 0, 0);
             else
               acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][ks], b[y][ks], acc[x][y], 0, 0, 0);
           }
@@ -753,7 +769,8 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
                          : NI_ <= 2 && NJ_ <= 2 &&                                       \
                                kernel_of((2 * NI_ - 1) * 4 + 2 * NJ_ - 1, 1) == KID)     \
       if constexpr (GEN) run_tiles<V, NI_, NJ_, GEN, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd); \
-      else run_steps<V, NI_, NJ_, CIN, BATCH, DP>(P, e0, e1, r, n / kXcd);                 \
+      else if (P.mo == kRowSplit) run_steps<V, NI_, NJ_, CIN, BATCH, DP, true>(P, e0, e1, r, n / kXcd); \
+      else run_steps<V, NI_, NJ_, CIN, BATCH, DP, false>(P, e0, e1, r, n / kXcd);        \
     break;
     BSM_SHAPE(1, 1) BSM_SHAPE(1, 2) BSM_SHAPE(1, 3) BSM_SHAPE(1, 4)
     BSM_SHAPE(2, 1) BSM_SHAPE(2, 2) BSM_SHAPE(2, 3) BSM_SHAPE(2, 4)

@@ -5,7 +5,7 @@ phase on the GPU (coordinate descent over the 16 classes starting from the
 built-in table, then a scan of panel edges), and writes the result as JSON
 for bsm_tune_load.
 
-Usage: python -m paper_1910_13555_amd.tune [--workload banded|batched|tall_skinny]
+Usage: python -m paper_1910_13555_amd.tune [--workload banded|batched|tall_skinny|rank3]
                                            [--out FILE] [--reps N]
 """
 from __future__ import annotations
@@ -37,6 +37,17 @@ def _runner(name):
         outs = batch.execute(1.0, a, b)
         keep = (mats, plans, batch, outs)
         return (lambda: batch.execute(1.0, a, b, out=outs)), keep
+    if name == "rank3":   # the contraction T[mu,nu,P] M[nu,lambda] -> R[mu,lambda,P]
+        import numpy as np
+        d = workloads.rank3()
+        sz = d["sizes"]
+        T = bsm.BlockSparseTensor.from_lists([sz["mu"], sz["nu"], sz["P"]], d["T_idx"], d["T_values"], ctx=ctx)
+        Mi = np.stack([d["M_rows"], d["M_cols"]], 1).astype(np.int32)
+        M = bsm.BlockSparseTensor.from_lists([sz["nu"], sz["lam"]], Mi, d["M_values"], ctx=ctx)
+        plan = bsm.bsm_contract_plan(ctx, "mnP,nl->mlP", T.pattern, T.values, M.pattern, M.values)
+        out = torch.empty(plan.info["c_nvals"], dtype=torch.float64, device="cuda")
+        keep = (T, M, plan, out)
+        return (lambda: plan.execute(1.0, T.values, M.values, 0.0, None, out)), keep
     d = {"banded": workloads.banded, "tall_skinny": workloads.tall_skinny}[name]()
     A = bsm.BlockSparseMatrix.from_workload(d["A"], ctx=ctx)
     B = bsm.BlockSparseMatrix.from_workload(d["B"], ctx=ctx)
@@ -81,9 +92,10 @@ def tune(workload="banded", reps=10, min_gain=0.02):
             table, best = trial, t
     bsm.bsm_tune_set(table)
     del keep, fn
-    # work order: output panel edge (plans are rebuilt, the order is fixed at plan time)
+    # work order: output panel edge (plans are rebuilt, the order is fixed at plan time;
+    # not scanned for the rank-3 contraction, whose inputs take minutes to regenerate)
     panel = bsm.bsm_tune_get_panel()
-    for edge in (16, 32, 64):
+    for edge in (() if workload == "rank3" else (16, 32, 64)):
         bsm.bsm_tune_panel(edge, edge)
         fn, keep = _runner(workload)
         t = _time(fn, reps)
@@ -98,7 +110,7 @@ def tune(workload="banded", reps=10, min_gain=0.02):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="banded", choices=["banded", "batched", "tall_skinny"])
+    ap.add_argument("--workload", default="banded", choices=["banded", "batched", "tall_skinny", "rank3"])
     ap.add_argument("--out", default=None, help="JSON file (default: tuned/<workload>.json here)")
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()

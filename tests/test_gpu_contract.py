@@ -200,3 +200,44 @@ def test_chained_output_pattern(bsm):
     assert sorted(got2.blocks) == sorted(ref2.blocks)
     if ref2.blocks:
         assert_tensor_close(got2, ref2, TOL)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("with_t3", [False, True])
+def test_split_output_rows_both_variants(bsm, variant, with_t3):
+    """Output in split rows (mu, P) x lambda with tall rows spanning several
+    tiles and split factors 23 / 35, under each matrix-core variant for every
+    tile class; with T3 the C_in values are read in split rows as well, from
+    blocks stored in tensor order (not the matrix order of the output)."""
+    rng = np.random.default_rng(5150 + 2 * variant + with_t3)
+    sz = {"m": rng.choice([5, 13], size=3).astype(np.int32), "n": rng.choice([5, 13], size=4).astype(np.int32),
+          "l": rng.choice([5, 13], size=3).astype(np.int32), "P": rng.choice([23, 35], size=2).astype(np.int32)}
+    d1 = workloads.random_tensor(rng, [sz[c] for c in "mnP"], 0.6)
+    d2 = workloads.random_tensor(rng, [sz[c] for c in "nl"], 0.7)
+    d3 = workloads.random_tensor(rng, [sz[c] for c in "mlP"], 0.4) if with_t3 else None
+    alpha, beta = (1.5, 0.75) if with_t3 else (1.0, 0.0)
+    T3 = to_lib(bsm, d3) if d3 else None
+    if T3 is not None:
+        T3.values.requires_grad_(True)
+    saved = bsm.bsm_tune_get()
+    try:
+        bsm.bsm_tune_set([variant] * 16)
+        R = bsm.contract("mnP,nl->mlP", to_lib(bsm, d1), to_lib(bsm, d2), T3, alpha, beta)
+        torch.cuda.synchronize()
+        if T3 is not None:   # dT3 = beta * dR on T3's blocks, T3 stored in its own (tensor) order
+            g = torch.from_numpy(rng.standard_normal(R.values.numel())).to(R.values.device)
+            R.values.backward(g)
+            torch.cuda.synchronize()
+    finally:
+        bsm.bsm_tune_set(saved)
+    ref, pairs = ot.contract(to_ref(d1), to_ref(d2), "mnP,nl->mlP", to_ref(d3) if d3 else None, alpha, beta)
+    assert R.plan.info["nprod"] == len(pairs)
+    got = tensor_to_oracle(R.pattern, R.values, ref.mode_sizes)
+    assert sorted(got.blocks) == sorted(ref.blocks)
+    if ref.blocks:
+        assert_tensor_close(got, ref, TOL)
+    if T3 is not None:
+        gr = tensor_to_oracle(R.pattern, g, ref.mode_sizes)
+        d3g = tensor_to_oracle(T3.pattern, T3.values.grad, ref.mode_sizes)
+        for k, blk in d3g.blocks.items():
+            np.testing.assert_array_equal(blk, beta * gr.blocks[k])
