@@ -251,13 +251,13 @@ void validate_mm(bsm_pattern A, bsm_pattern B, bsm_pattern C, double eps, const 
   const auto& bcs = o.trans_b ? B->h_rs : B->h_cs;
   if (aks != bks) fail(BSM_E_SHAPE, "inner block sizes of op(A) and op(B) differ");
   // the kernels address a block's values with 32-bit byte offsets below 2 GB
-  auto big = [](const std::vector<int32_t>& r, const std::vector<int32_t>& c) {
-    const int64_t mr = r.empty() ? 0 : *std::max_element(r.begin(), r.end());
-    const int64_t mc = c.empty() ? 0 : *std::max_element(c.begin(), c.end());
-    return mr * mc >= (int64_t(1) << 28);
-  };
-  if (big(ars, aks) || big(bks, bcs) || big(ars, bcs))
-    fail(BSM_E_UNSUPPORTED, "blocks of 2^28 or more values (2 GB) are not supported");
+  {
+    const int64_t am = o.trans_a ? A->max_cs() : A->max_rs(), ak = o.trans_a ? A->max_rs() : A->max_cs();
+    const int64_t bk = o.trans_b ? B->max_cs() : B->max_rs(), bn = o.trans_b ? B->max_rs() : B->max_cs();
+    const int64_t lim = int64_t(1) << 28;
+    if (am * ak >= lim || bk * bn >= lim || am * bn >= lim)
+      fail(BSM_E_UNSUPPORTED, "blocks of 2^28 or more values (2 GB) are not supported");
+  }
   if (C) {
     C->ensure_host();
     if (C->h_rs != ars || C->h_cs != bcs) fail(BSM_E_SHAPE, "C block sizes do not match op(A) rows / op(B) columns");

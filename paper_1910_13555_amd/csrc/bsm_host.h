@@ -287,6 +287,16 @@ struct bsm_pattern_s {
   DBuf<int64_t> d_off;
 
   int32_t stored(int64_t e) const { return h_blk.empty() ? (int32_t)e : h_blk[e]; }
+  // largest row / column block size, cached (needs the host index)
+  int32_t mrs = -1, mcs = -1;
+  int32_t max_rs() {
+    if (mrs < 0) mrs = h_rs.empty() ? 0 : *std::max_element(h_rs.begin(), h_rs.end());
+    return mrs;
+  }
+  int32_t max_cs() {
+    if (mcs < 0) mcs = h_cs.empty() ? 0 : *std::max_element(h_cs.begin(), h_cs.end());
+    return mcs;
+  }
   // transposed index (CSC), built on demand
   bool t_valid = false;
   std::vector<int32_t> h_tptr, h_trow, h_tblk;

@@ -239,3 +239,18 @@ def test_plan_stacks_match_oracle(bsm, seed):
     rows, cols, _ = pat.export()
     assert sorted(zip(rows.tolist(), cols.tolist())) == sorted(ref.blocks)
     assert stack_triples(plan, A, B, False, False, pat) == sorted(trip)
+
+
+def test_plan_rejects_blocks_of_2gb(bsm):
+    """Blocks are addressed with 32-bit byte offsets: a plan whose largest
+    blocks could reach 2^28 values is refused before any device work; one
+    just below is planned."""
+    ctx = bsm.default_context()
+    A, _ = bsm.bsm_pattern_create(ctx, [16384], [16384], [0], [0])
+    B, _ = bsm.bsm_pattern_create(ctx, [16384], [1], [0], [0])
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.bsm_multiply_plan(ctx, A, None, B, None)
+    assert e.value.code == -6
+    A2, _ = bsm.bsm_pattern_create(ctx, [16383], [16384], [0], [0])
+    plan = bsm.bsm_multiply_plan(ctx, A2, None, B, None)
+    assert plan.info["nprod"] == 1 and plan.info["c_nvals"] == 16383
