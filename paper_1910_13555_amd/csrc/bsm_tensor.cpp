@@ -34,11 +34,10 @@ struct bsm_tpattern_s {
   // numbers on the device and fills idx and off on first use (export or a
   // later contraction), so that producing it costs no host pass.
   std::function<void(bsm_tpattern_s&)> pending;
-  void ensure() {
+  void ensure() {   // kept pending if filling fails (a device error), so no half-filled list is used
     if (!pending) return;
-    auto f = std::move(pending);
+    pending(*this);
     pending = nullptr;
-    f(*this);
   }
   int32_t bsize(int64_t b, int m) const { return sz[m][idx[b * rank + m]]; }
 };
