@@ -8,7 +8,9 @@ before timing starts.  Prints one JSON line, which also carries the
 roofline of the dominant numeric kernel (timed live with HIP events on the
 library's stream), the split-precision forms on the same workload and the
 64-problem batch (FP64 and bf16x3, replayed from a HIP graph), each with its
-error against FP64, and the CPU oracle's rate on a bounded sample.
+error against FP64, the tall-skinny multiply, the rank-3 contraction
+(forward and forward + backward, with the forward's fraction of the HBM
+roofline) and the CPU oracle's rate on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
        python bench.py --traffic-from FETCH_CSV WRITE_CSV --copy-bytes N
@@ -326,8 +328,12 @@ def rank3_section(bsm, reps, stream):
         out.values.backward(g)
     torch.cuda.synchronize()
     fb_ms = (time.perf_counter() - t0) * 1e3 / reps
+    # the forward is bound by HBM: R written once (beta = 0) and T, M read once
+    comp = 8.0 * (out.values.numel() + T.values.numel() + M.values.numel())
     return {"workload": d["name"], "products": out.plan.info["nprod"], "useful_gflop_forward": F / 1e9,
             "forward_ms": fwd_ms, "forward_gflops": F / (fwd_ms * 1e-3) / 1e9,
+            "forward_compulsory_gb": comp / 1e9,
+            "forward_hbm_frac": comp / (fwd_ms * 1e-3) / PEAK_HBM,
             "forward_backward_ms": fb_ms, "forward_backward_gflops": 3 * F / (fb_ms * 1e-3) / 1e9}
 
 
@@ -342,7 +348,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the split-precision and batched sections")
     ap.add_argument("--rank3", action="store_true",
-                    help="also run the rank-3 contraction (13.5 GB tensor; about a minute of setup)")
+                    help="run the rank-3 contraction (13.5 GB tensor; about a minute of setup) also "
+                         "with --no-extra (the default run includes it)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device-to-device copy of this many bytes "
                          "(calibrates HBM byte counters of a profiler run)")
@@ -449,12 +456,16 @@ def main():
         torch.cuda.empty_cache()
         res["batched"] = batched_section(bsm, max(2, args.steps // 4), stream)
         res["tall_skinny"] = tall_skinny_section(bsm, max(2, args.steps // 4), stream)
-    if args.rank3:
+    if args.rank3 or not args.no_extra:
         tuned = os.path.join(ROOT, "paper_1910_13555_amd", "tuned", "rank3.json")
         if os.path.exists(tuned):
             bsm.bsm_tune_load(tuned)      # the autotuner's table for this workload
-        res["rank3"] = rank3_section(bsm, 3, stream)
-        res["rank3"]["tuning"] = bsm.bsm_tune_get()
+        try:
+            res["rank3"] = rank3_section(bsm, 3, stream)
+            res["rank3"]["tuning"] = bsm.bsm_tune_get()
+        except (RuntimeError, MemoryError) as e:   # reported, not fatal to the main line
+            res["rank3"] = {"error": str(e)[:300]}
+        torch.cuda.empty_cache()
         bsm.bsm_tune_load(TUNED)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d)
