@@ -291,9 +291,18 @@ def tall_skinny_section(bsm, reps, stream):
     del plans
     ms = time_events(lambda: plan.execute(d["alpha"], A.values, B.values, d["beta"], cin, cin), reps, stream)
     F = plan.info["flops"]
+    # bound by HBM: touched A and B blocks read once, the C blocks that get
+    # products read and written once (the others are left untouched in place)
+    import numpy as np
+    a, b, c = plan.export_stack()
+    lens = lambda pat, n: np.diff(np.append(pat.export()[2], n))
+    comp = 8 * (int(lens(A.pattern, A.pattern.nvals)[np.unique(a)].sum())
+                + int(lens(B.pattern, B.pattern.nvals)[np.unique(b)].sum())
+                + 2 * int(lens(plan.c_pattern(), plan.info["c_nvals"])[np.unique(c)].sum()))
     return {"workload": d["name"], "products": plan.info["nprod"], "useful_gflop": F / 1e9,
             "ms_per_multiply": full_ms, "gflops": F / (full_ms * 1e-3) / 1e9,
-            "numeric_ms": ms, "numeric_gflops": F / (ms * 1e-3) / 1e9}
+            "numeric_ms": ms, "numeric_gflops": F / (ms * 1e-3) / 1e9,
+            "numeric_compulsory_mb": comp / 1e6, "numeric_hbm_frac": comp / (ms * 1e-3) / PEAK_HBM}
 
 
 def rank3_section(bsm, reps, stream):
