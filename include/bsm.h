@@ -99,8 +99,8 @@ bsm_status bsm_ctx_destroy(bsm_ctx ctx);
 bsm_status bsm_ctx_set_timing(bsm_ctx ctx, int32_t on);
 bsm_status bsm_ctx_launch_times(bsm_ctx ctx, float* ms_out);
 /* Concurrent kernel families (default on): the FP64 numeric launches of one
- * execute after the first go to side streams of the context (default
- * priority), forked from and joined back into the context's stream with
+ * execute or gradient after the first go to side streams of the context
+ * (default priority), forked from and joined back into the context's stream with
  * events, so their waves fill the device while earlier families drain.
  * Results are identical either way (every output tile belongs to one
  * family); with on == 0 the launches run one after another on the context's
