@@ -25,15 +25,32 @@ __global__ void __launch_bounds__(256) k_remap(int64_t nblk, const int64_t* __re
   const int td[4] = {d[pm[0]], d[pm[1]], d[pm[2]], d[pm[3]]};
   const int64_t o = off[b];
   const int n = d[0] * d[1] * d[2] * d[3];
-  for (int e = l; e < n; e += 64) {
-    int rem = e, s = 0;
+  // target index e as mixed-radix digits (td[3] fastest), advanced by 64 per
+  // pass by digit-wise addition with carry (no division in the loop); when
+  // n <= 64 the digits of 64 overflow, but then no lane makes a second pass
+  int ta[4], inc[4];
+  {
+    int x = l, r = 64;
+#pragma unroll
     for (int a = 3; a >= 0; --a) {
-      const int ta = rem % td[a];
-      rem /= td[a];
-      s += ta * sstride[pm[a]];
+      ta[a] = x % td[a];
+      x /= td[a];
+      inc[a] = r % td[a];
+      r /= td[a];
     }
+  }
+  const int ss[4] = {sstride[pm[0]], sstride[pm[1]], sstride[pm[2]], sstride[pm[3]]};
+  for (int e = l; e < n; e += 64) {
+    const int s = ta[0] * ss[0] + ta[1] * ss[1] + ta[2] * ss[2] + ta[3] * ss[3];
     if (inverse) dst[o + s] = src[o + e];
     else dst[o + e] = src[o + s];
+    int carry = 0;
+#pragma unroll
+    for (int a = 3; a >= 0; --a) {
+      const int t = ta[a] + inc[a] + carry;
+      carry = t >= td[a];
+      ta[a] = carry ? t - td[a] : t;
+    }
   }
 }
 
