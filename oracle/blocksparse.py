@@ -36,9 +36,15 @@ in increasing e, starting from 0.0; the 64 partial sums are then added
 pairwise, lane l with lane l+h for h = 32, 16, 8, 4, 2, 1.  Every square and
 every addition is rounded separately (no fused multiply-add).
 
+Rounding bounds: ``multiply_error_bound`` and ``backward_error_bound`` give
+the elementwise tolerance of the float64 parity checks, from the standard
+bound on a floating-point sum of products (any order, each operation rounded
+once).
+
 Parity status: every function here is pinned by tests/test_oracle.py
 (brute force on tiny grids, dense BLAS special cases, scipy.sparse symbolic
-product, exact-arithmetic norms, invariants).
+product, exact-arithmetic norms, invariants; the rounding bounds against
+exact rational arithmetic and a worst-case sum).
 """
 from __future__ import annotations
 
@@ -357,6 +363,74 @@ def multiply_backward(A, B, C, dC, triples, alpha=1.0, beta=0.0,
         dCin = BlockSparse(C.row_sizes, C.col_sizes,
                            {k: beta * dC.blocks[k] for k in C.blocks})
     return dA, dB, dCin
+
+
+# --------------------------------------------------------- rounding bounds
+
+UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def gamma(n: int) -> float:
+    """gamma_n = n*u / (1 - n*u), u = 2^-53: relative bound, against the sum of
+    the terms' magnitudes, on the error of a float64 sum of n terms evaluated
+    in any order, each term a product rounded at most once (an FMA chain
+    rounds less, never more)."""
+    return n * UNIT_ROUNDOFF / (1.0 - n * UNIT_ROUNDOFF)
+
+
+def _abs_copy(m):
+    if m is None:
+        return None
+    return BlockSparse(m.row_sizes, m.col_sizes, {k: np.abs(b) for k, b in m.blocks.items()})
+
+
+def multiply_error_bound(A, B, C=None, alpha=1.0, beta=0.0, eps=0.0, trans_a=False, trans_b=False,
+                         retain_sparsity=False, rows=None):
+    """Elementwise bound on |x - y| for two float64 evaluations x, y of the
+    multiply (same kept set, any order of the sum over k: the reading that
+    leaves that order free).  For element (r, c) of output block (i, j) with
+    n scalar products summed into it (the K of every kept product of the
+    block):
+        2 * gamma_{n+3} * (|alpha| * sum |A_ik||B_kj| + |beta| |C_in|)(r, c)
+    -- gamma_n for the sum, one rounding each for the alpha scaling, the beta
+    product and the final addition; the factor 2 covers both evaluations.
+    Returns {output block: array of bounds}."""
+    nA = norms(A)
+    nB = norms(B)
+    S, triples = multiply(_abs_copy(A), _abs_copy(B), _abs_copy(C), abs(alpha), abs(beta), eps,
+                          trans_a, trans_b, retain_sparsity, rows, norms_a=nA, norms_b=nB)
+    ks = A.row_sizes if trans_a else A.col_sizes
+    n = {k: 0 for k in S.blocks}
+    for i, k, j in triples:
+        n[(i, j)] += int(ks[k])
+    return {key: 2.0 * gamma(n[key] + 3) * blk for key, blk in S.blocks.items()}
+
+
+def backward_error_bound(A, B, dC, triples, alpha=1.0, trans_a=False, trans_b=False, C=None, beta=0.0):
+    """Elementwise bounds (dA, dB, dC_in), as BlockSparse in the stored
+    layouts, on the difference of two float64 evaluations of the gradient of
+    ``multiply_backward``: 2 gamma_{n+1} |alpha| sum |dC||B|^T for dA (n = the
+    columns summed over the kept j), likewise for dB (n = the rows summed over
+    the kept i); 2 gamma_1 |beta| |dC| for dC_in (None without C)."""
+    dA, dB, _ = multiply_backward(_abs_copy(A), _abs_copy(B), None, _abs_copy(dC), triples,
+                                  abs(alpha), 0.0, trans_a, trans_b)
+    rs = A.col_sizes if trans_a else A.row_sizes
+    cs = B.row_sizes if trans_b else B.col_sizes
+    na, nb = {}, {}
+    for i, k, j in triples:
+        na[(i, k)] = na.get((i, k), 0) + int(cs[j])
+        nb[(k, j)] = nb.get((k, j), 0) + int(rs[i])
+    ka = (lambda key: (key[1], key[0])) if trans_a else (lambda key: key)
+    kb = (lambda key: (key[1], key[0])) if trans_b else (lambda key: key)
+    bA = BlockSparse(dA.row_sizes, dA.col_sizes,
+                     {key: 2.0 * gamma(na.get(ka(key), 0) + 1) * b for key, b in dA.blocks.items()})
+    bB = BlockSparse(dB.row_sizes, dB.col_sizes,
+                     {key: 2.0 * gamma(nb.get(kb(key), 0) + 1) * b for key, b in dB.blocks.items()})
+    bC = None
+    if C is not None:
+        bC = BlockSparse(C.row_sizes, C.col_sizes,
+                         {key: 2.0 * gamma(1) * abs(beta) * np.abs(dC.blocks[key]) for key in C.blocks})
+    return bA, bB, bC
 
 
 # ---------------------------------------------------------------- helpers

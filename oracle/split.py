@@ -58,13 +58,16 @@ def block_product(a, b, scheme: str):
     return out
 
 
-def multiply_split(A, B, C=None, alpha=1.0, beta=0.0, eps=0.0, scheme="bf16x3"):
+def multiply_split(A, B, C=None, alpha=1.0, beta=0.0, eps=0.0, scheme="bf16x3", rows=None):
     """C_out = beta*C_in + alpha*sum(split products); returns (C_out, bound).
 
     ``bound`` maps each output block to an elementwise bound on the float32
-    accumulation error of the GPU's sum (see ``accumulation_bound``)."""
-    triples = kept_products(A, B, C, eps)
+    accumulation error of the GPU's sum (see ``accumulation_bound``).
+    ``rows`` restricts the computation to a set of output block rows."""
+    triples = kept_products(A, B, C, eps, rows=rows)
     keys = output_pattern(C, triples)
+    if rows is not None:
+        keys = [k for k in keys if k[0] in rows]
     npieces, terms = SCHEMES[scheme]
     acc, absacc, klen = {}, {}, {}
     for (i, k, j) in triples:
@@ -90,10 +93,14 @@ def multiply_split(A, B, C=None, alpha=1.0, beta=0.0, eps=0.0, scheme="bf16x3"):
 
 
 def accumulation_bound(klen: int, nterms: int) -> float:
-    """Relative (to sum |a||b|) bound on a float32 sum of klen*nterms exact
-    products: gamma_n = n*u/(1-n*u) with u = 2^-24, plus one float32 rounding
-    per piece product kept exact (none) -- a factor 2 margin is added for the
-    products of pieces that are not exact in float32 (none for bf16)."""
+    """Bound, relative to sum |a||b| over the run, on the float32 error of
+    the GPU's sum of an output element's piece products.  A product of two
+    bfloat16 pieces (8 significant bits each) is exact in float32, so the
+    only error is the float32 summation of n = klen * nterms such products
+    plus the one float32 value the run's sum starts from: gamma_n =
+    n u / (1 - n u) with u = 2^-24 for n = klen * nterms + 1 terms in any
+    order, times 2 as a margin (the pieces' magnitudes are bounded by |x|
+    only up to float32 rounding of x)."""
     u = 2.0 ** -24
     n = klen * nterms + 1
     return 2.0 * n * u / (1.0 - n * u)

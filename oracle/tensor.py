@@ -25,13 +25,14 @@ Readings fixed here (the paper gives no formulas):
 
 Parity status: pinned by tests/test_oracle_tensor.py (dense np.einsum on
 fully dense tensors, equality with the matrix route, exact finite
-differences of the gradient).
+differences of the gradient, the rounding bounds against exact rational
+arithmetic).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .blocksparse import BlockSparse, block_norm_sq, multiply
+from .blocksparse import BlockSparse, block_norm_sq, gamma, multiply
 
 
 class BlockSparseTensor:
@@ -136,6 +137,55 @@ def contract_backward(T1, T2, spec, dT3, pairs, alpha=1.0):
         d1[k1] += alpha * np.einsum(f"{out},{s2}->{s1}", g, T2.blocks[k2])
         d2[k2] += alpha * np.einsum(f"{out},{s1}->{s2}", g, T1.blocks[k1])
     return BlockSparseTensor(T1.mode_sizes, d1), BlockSparseTensor(T2.mode_sizes, d2)
+
+
+# ----------------------------------------------------------- rounding bounds
+
+def _abs_tensor(T):
+    if T is None:
+        return None
+    return BlockSparseTensor(T.mode_sizes, {k: np.abs(b) for k, b in T.blocks.items()})
+
+
+def contract_error_bound(T1, T2, spec, T3=None, alpha=1.0, beta=0.0, eps=0.0):
+    """Elementwise bound on the difference of two float64 evaluations of
+    ``contract`` (the order of the sum over the summed indices is free):
+    2 gamma_{n+3} (|alpha| sum |T1||T2| + |beta| |T3_in|), n = the scalar
+    products summed into the element (the summed extent of every kept pair
+    of its block).  Returns {output block: array of bounds}."""
+    s1, s2, out, con = parse_spec(spec)
+    S, pairs = contract(_abs_tensor(T1), _abs_tensor(T2), spec, _abs_tensor(T3), abs(alpha), abs(beta), eps)
+    n = {k: 0 for k in S.blocks}
+    for k1, k2 in pairs:
+        ext = 1
+        for c in con:
+            ext *= int(T1.mode_sizes[s1.index(c)][k1[s1.index(c)]])
+        n[tuple(k1[s1.index(c)] if c in s1 else k2[s2.index(c)] for c in out)] += ext
+    return {key: 2.0 * gamma(n[key] + 3) * b for key, b in S.blocks.items()}
+
+
+def contract_backward_error_bound(T1, T2, spec, dT3, pairs, alpha=1.0):
+    """Elementwise bounds (for T1's and T2's gradients) on the difference of
+    two float64 evaluations of ``contract_backward``: 2 gamma_{n+1} |alpha|
+    times the same contraction of the magnitudes, n = the scalar products
+    summed into the element (the output extent of each kept pair)."""
+    s1, s2, out, _ = parse_spec(spec)
+    g1, g2 = contract_backward(_abs_tensor(T1), _abs_tensor(T2), spec, _abs_tensor(dT3), pairs, abs(alpha))
+    n1, n2 = {}, {}
+    for k1, k2 in pairs:
+        e1 = 1   # output elements per element of T1's block: T2's free extent
+        for c in out:
+            if c in s2:
+                e1 *= int(T2.mode_sizes[s2.index(c)][k2[s2.index(c)]])
+        e2 = 1   # and T1's free extent for T2's
+        for c in out:
+            if c in s1:
+                e2 *= int(T1.mode_sizes[s1.index(c)][k1[s1.index(c)]])
+        n1[k1] = n1.get(k1, 0) + e1
+        n2[k2] = n2.get(k2, 0) + e2
+    b1 = {k: 2.0 * gamma(n1.get(k, 0) + 1) * b for k, b in g1.blocks.items()}
+    b2 = {k: 2.0 * gamma(n2.get(k, 0) + 1) * b for k, b in g2.blocks.items()}
+    return b1, b2
 
 
 # ------------------------------------------------------------- matrix route
