@@ -45,6 +45,7 @@
 #ifndef BSM_H
 #define BSM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -83,6 +84,22 @@ int32_t bsm_version(void);
  * validated and exported, every call that needs the GPU returns
  * BSM_E_DEVICE. */
 bsm_status bsm_ctx_create(int32_t device, void* stream, bsm_ctx* out);
+/* Caller-supplied device allocator for the index memory of patterns, plans,
+ * batches and every temporary of the library's calls (the values stay the
+ * caller's own buffers in any case).  alloc_fn(bytes, device, stream, user)
+ * returns device memory of at least `bytes` on `device`, or NULL (the call
+ * that needed it then fails with BSM_E_NOMEM, writing no output and
+ * returning every block it had taken); free_fn(ptr, bytes, device, stream,
+ * user) takes a block back when its owner is destroyed or the call that used
+ * it returns.  `stream` is the context's stream: all device work that uses a
+ * block is queued there before the block is returned, so a stream-ordered
+ * allocator may hand it out again at once.  Both callbacks or neither (NULL:
+ * the library's own caching allocator, as bsm_ctx_create).  Blocks still
+ * held when the context is destroyed are returned then. */
+typedef void* (*bsm_alloc_fn)(size_t bytes, int32_t device, void* stream, void* user);
+typedef void (*bsm_free_fn)(void* ptr, size_t bytes, int32_t device, void* stream, void* user);
+bsm_status bsm_ctx_create_ex(int32_t device, void* stream, bsm_alloc_fn alloc_fn, bsm_free_fn free_fn,
+                             void* user, bsm_ctx* out);
 /* Switch the stream; work already queued on the old stream is waited for. */
 bsm_status bsm_ctx_set_stream(bsm_ctx ctx, void* stream);
 /* Wait for the context's stream; reports asynchronous device errors. */
@@ -98,6 +115,16 @@ bsm_status bsm_ctx_destroy(bsm_ctx ctx);
  * host-only context. */
 bsm_status bsm_ctx_set_timing(bsm_ctx ctx, int32_t on);
 bsm_status bsm_ctx_launch_times(bsm_ctx ctx, float* ms_out);
+/* Per-phase device time, with timing on (else BSM_E_INVALID): ms_out[4]
+ * (host array) = block norms, symbolic phase (product counts, their prefix
+ * sums, the size readback and the fill of the output pattern and product
+ * lists), step lists (row-major plans) of the last multiply plan created on
+ * this context, and the numeric phase (split pass included) of the last
+ * bsm_plan_execute; each is the time between HIP events recorded on the
+ * context's stream, -1 for a phase not timed since timing was switched on.
+ * Contraction plans report their matrix multiply's phases.  Kept and
+ * skipped product counts are in bsm_plan_info (nprod, ncand - nprod). */
+bsm_status bsm_ctx_phase_times(bsm_ctx ctx, float* ms_out);
 /* Concurrent kernel families (default on): the FP64 numeric launches of one
  * execute or gradient after the first go to side streams of the context
  * (default priority), forked from and joined back into the context's stream with
@@ -224,6 +251,17 @@ bsm_status bsm_plan_backward(bsm_plan plan, double alpha, const double* dc_vals,
  * values layout).  No-op without C_in. */
 bsm_status bsm_plan_cin_grad(bsm_plan plan, double beta, const double* dc_vals, double* dcin_vals);
 bsm_status bsm_plan_destroy(bsm_plan plan);
+/* Consistency check of a plan's index arrays on the host (for debugging and
+ * tests; it copies them back, so it costs about as much as the plan).  Each
+ * output tile must have exactly one owner (the static assignment of batches
+ * that keeps the paper's parallel execution free of races, Sec. 2), every
+ * product must name the stored blocks (i,k) of op(A) and (k,j) of op(B) of
+ * its output block (i,j), and every operand byte the numeric kernels address
+ * from the plan must lie inside that product's blocks.  BSM_OK, or
+ * BSM_E_INVALID with the first inconsistency in bsm_last_error().  With the
+ * environment variable BSM_DEBUG set (and not "0") every plan is checked
+ * when it is created, and a failing check fails the creating call. */
+bsm_status bsm_plan_check(bsm_plan plan);
 
 /* ------------------------------------------------------------ batches
  * Many independent multiplies of uneven sizes executed by one persistent

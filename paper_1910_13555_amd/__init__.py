@@ -60,15 +60,49 @@ def _ptr(t):
 
 # ---------------------------------------------------------------- context
 
+def torch_allocator():
+    """(alloc, free) callables that take the library's device memory from
+    torch's caching allocator, on the context's stream."""
+    def alloc(nbytes, device, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, device, stream or 0)
+
+    def free(ptr, nbytes, device, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
+
+
 class Context:
     """A libbsm context bound to one device and one stream (default: torch's
-    current stream of that device).  device=-1 gives a host-only context."""
+    current stream of that device).  device=-1 gives a host-only context.
 
-    def __init__(self, device: int = 0, stream=None):
+    allocator: None (the library's own caching allocator), "torch" (torch's
+    caching allocator), or a pair of callables alloc(nbytes, device, stream)
+    -> device address (0 for none) and free(address, nbytes, device, stream)."""
+
+    def __init__(self, device: int = 0, stream=None, allocator=None):
         if device >= 0 and stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
         h = C.c_void_p()
-        check(lib.bsm_ctx_create(device, C.c_void_p(stream or 0), C.byref(h)))
+        if allocator is None:
+            check(lib.bsm_ctx_create(device, C.c_void_p(stream or 0), C.byref(h)))
+        else:
+            alloc, free = torch_allocator() if allocator == "torch" else allocator
+
+            def c_alloc(nbytes, dev, st, _user):
+                try:
+                    return alloc(int(nbytes), int(dev), int(st or 0)) or None
+                except Exception:   # reported to the library as no memory
+                    return None
+
+            def c_free(ptr, nbytes, dev, st, _user):
+                try:
+                    free(int(ptr), int(nbytes), int(dev), int(st or 0))
+                except Exception:
+                    pass
+            # the callbacks live as long as the context object
+            self._callbacks = (_lib.ALLOC_FN(c_alloc), _lib.FREE_FN(c_free))
+            check(lib.bsm_ctx_create_ex(device, C.c_void_p(stream or 0), self._callbacks[0], self._callbacks[1],
+                                        None, C.byref(h)))
         self.handle = h
         self.device = device
         _live["ctx"].add(self)
@@ -86,6 +120,13 @@ class Context:
     def set_concurrent(self, on: bool):
         """Run the numeric kernel families of one execute concurrently (default) or in sequence."""
         check(lib.bsm_ctx_set_concurrent(self.handle, int(bool(on))))
+
+    def phase_times(self):
+        """Milliseconds of the last plan's norms, symbolic phase and step lists
+        and of the last execute's numeric phase (-1 where not timed)."""
+        out = (C.c_float * 4)()
+        check(lib.bsm_ctx_phase_times(self.handle, out))
+        return list(out)
 
     def launch_times(self):
         """Milliseconds of each numeric kernel family in the last execute (5 floats)."""
@@ -231,6 +272,10 @@ class Plan:
         check(lib.bsm_plan_backward(self.handle, float(alpha), _ptr(dc), _ptr(a_vals), _ptr(b_vals),
                                     _ptr(da), _ptr(db)))
         return da, db
+
+    def check(self):
+        """Host-side consistency check of the plan's index arrays (bsm_plan_check)."""
+        check(lib.bsm_plan_check(self.handle))
 
     def cin_grad(self, dc, beta):
         """dC_in = beta * dC on pat(C_in)."""

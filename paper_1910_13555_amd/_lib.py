@@ -71,6 +71,7 @@ PROTOTYPES = {
     "bsm_plan_backward": [_vp, C.c_double, _dp, _dp, _dp, _dp, _dp],
     "bsm_plan_cin_grad": [_vp, C.c_double, _dp, _dp],
     "bsm_plan_destroy": [_vp],
+    "bsm_plan_check": [_vp],
     "bsm_batch_create": [_vp, C.c_int32, C.POINTER(_vp), C.POINTER(_vp)],
     "bsm_batch_execute": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_vp),
                           C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int32],
@@ -86,6 +87,8 @@ PROTOTYPES = {
     "bsm_ctx_set_timing": [_vp, C.c_int32],
     "bsm_ctx_set_concurrent": [_vp, C.c_int32],
     "bsm_ctx_launch_times": [_vp, C.POINTER(C.c_float)],
+    "bsm_ctx_phase_times": [_vp, C.POINTER(C.c_float)],
+    "bsm_ctx_create_ex": [C.c_int32, _vp, "ALLOC_FN", "FREE_FN", _vp, C.POINTER(_vp)],
     "bsm_tune_load": [C.c_char_p],
     "bsm_tune_panel": [C.c_int32, C.c_int32],
     "bsm_tune_get_panel": [_i32p, _i32p],
@@ -93,6 +96,10 @@ PROTOTYPES = {
     "bsm_tune_set": [_i32p],
 }
 _RESTYPE = {"bsm_last_error": C.c_char_p, "bsm_version": C.c_int32}
+# caller allocator callbacks of bsm_ctx_create_ex
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p, C.c_void_p)
+_CALLBACKS = {"ALLOC_FN": ALLOC_FN, "FREE_FN": FREE_FN}
 
 
 def _load():
@@ -102,7 +109,7 @@ def _load():
     lib = C.CDLL(LIB_PATH)
     for name, args in PROTOTYPES.items():
         fn = getattr(lib, name)
-        fn.argtypes = args
+        fn.argtypes = [_CALLBACKS.get(a, a) if isinstance(a, str) else a for a in args]
         fn.restype = _RESTYPE.get(name, C.c_int32)
     return lib
 

@@ -78,6 +78,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
   P.cs = tb ? B->d_rs.p : B->d_cs.p;
   P.eps2 = pl->eps * pl->eps;
   P.retain = pl->opts.retain_sparsity;
+  ctx->mark(ctx->plan_ev[0]);
   if (C) {
     P.cin_ptr = C->d_ptr.p;
     P.cin_col = C->d_col.p;
@@ -108,6 +109,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     P.a.nrm = pl->na.p;
     P.b.nrm = pl->nb.p;
   }
+  ctx->mark(ctx->plan_ev[1]);
   const int32_t nr = pl->nr;
   pl->c_rs = P.rs;
   pl->c_cs = P.cs;
@@ -150,6 +152,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                             pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->tasks.p,
                             pl->step_path() ? pblk.p : nullptr),
             "symbolic fill");
+  ctx->mark(ctx->plan_ev[2]);
   // in place only where C_out's packing is C_in's (same blocks, canonical order)
   pl->c_same_as_cin = C && pl->c_nblk == C->nblk && C->h_blk.empty();
   if (g_panel[0] > 0 && pl->ntasks > 1) {
@@ -206,6 +209,8 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
                                    pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
               "product steps");
   }
+  ctx->mark(ctx->plan_ev[3]);
+  ctx->plan_timed = ctx->timing;
   // temporaries go back to the allocator: later work on this stream is ordered after the fill
 }
 
@@ -264,13 +269,25 @@ void validate_mm(bsm_pattern A, bsm_pattern B, bsm_pattern C, double eps, const 
   }
 }
 
+// Bytes of piece arrays a split-precision execute needs: both operands'
+// arrays, each starting on a 256-byte boundary.
+size_t split_scratch_bytes(bsm_plan pl) {
+  if (pl->opts.precision == BSM_PREC_FP64) return 0;
+  const int np = split_pieces(pl->opts.precision);
+  const size_t xa = ((size_t)np * piece_stride(pl->apad_n) * 2 + 255) & ~size_t(255);
+  return xa + (size_t)np * piece_stride(pl->bpad_n) * 2;
+}
+
 void execute(bsm_plan pl, double alpha, const double* x, const double* y, double beta,
-             const double* cin, double* out) {
+             const double* cin, double* out, const Scratch* sc) {
   if (!out && pl->c_nvals > 0) fail(BSM_E_INVALID, "NULL output");
   if (beta != 0.0 && pl->Cin && pl->Cin->nblk > 0 && !cin) fail(BSM_E_INVALID, "beta != 0 needs C_in values");
   if (pl->nprod > 0 && (!x || !y)) fail(BSM_E_INVALID, "NULL operand values");
   if (out == cin && cin && !pl->c_same_as_cin)
     fail(BSM_E_INVALID, "c_out may alias c_in only when the output pattern equals C_in's");
+  if (sc && split_scratch_bytes(pl) > sc->bytes)
+    fail(BSM_E_UNSUPPORTED, "split precision needs %zu bytes of piece arrays; the fixed scratch holds %zu",
+         split_scratch_bytes(pl), sc->bytes);
   set_device(pl->ctx);
   NumParams P;
   P.out = out;
@@ -301,25 +318,44 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
     P.ev = pl->ctx->ev;
     P.launched = pl->ctx->launched;
   }
-  attach_side_streams(pl->ctx, P);
+  // side streams are created on first use, except by an allocation-free
+  // execute (sc), which runs the families one after another until they exist
+  attach_side_streams(pl->ctx, P, !sc);
+  bsm_ctx ctx = pl->ctx;
+  ctx->mark(ctx->exec_ev[0]);
+  ctx->exec_timed = ctx->timing;
   if (pl->opts.precision == BSM_PREC_FP64) {
     hip_check(launch_numeric(pl->ctx->stream, generic, P), "numeric");
+    ctx->mark(ctx->exec_ev[1]);
     return;
   }
-  // split precision: piece arrays of both operands (freed to the context's
-  // allocator after the launch; later work on the stream is ordered after it)
+  // split precision: piece arrays of both operands, from the context's
+  // allocator (returned after the launch; later work on the stream is ordered
+  // after it) or from the caller's fixed scratch
   const int np = split_pieces(pl->opts.precision);
   hipStream_t st = pl->ctx->stream;
   const int64_t sx = piece_stride(pl->apad_n), sy = piece_stride(pl->bpad_n);
-  DBuf<uint16_t> xp(pl->ctx, (size_t)np * sx), yp(pl->ctx, (size_t)np * sy);
-  if (pl->nprod > 0) {  // else every tile is empty and no operand is read
-    split_operands(pl, np, x, y, sx, sy, xp.p, yp.p, st);
+  DBuf<uint16_t> xbuf, ybuf;
+  uint16_t* xp;
+  uint16_t* yp;
+  if (sc) {
+    xp = static_cast<uint16_t*>(sc->p);
+    yp = reinterpret_cast<uint16_t*>(static_cast<char*>(sc->p) + (((size_t)np * sx * 2 + 255) & ~size_t(255)));
+  } else {
+    xbuf = DBuf<uint16_t>(pl->ctx, (size_t)np * sx);
+    ybuf = DBuf<uint16_t>(pl->ctx, (size_t)np * sy);
+    xp = xbuf.p;
+    yp = ybuf.p;
   }
-  P.X = reinterpret_cast<const double*>(xp.p);
-  P.Y = reinterpret_cast<const double*>(yp.p);
+  if (pl->nprod > 0) {  // else every tile is empty and no operand is read
+    split_operands(pl, np, x, y, sx, sy, xp, yp, st);
+  }
+  P.X = reinterpret_cast<const double*>(xp);
+  P.Y = reinterpret_cast<const double*>(yp);
   P.xpb = (uint32_t)(2 * sx);
   P.ypb = (uint32_t)(2 * sy);
   hip_check(launch_numeric_split(st, np, P), "split numeric");
+  ctx->mark(ctx->exec_ev[1]);
 }
 
 template <class G>
@@ -488,8 +524,14 @@ const char* bsm_last_error(void) { return g_err.c_str(); }
 int32_t bsm_version(void) { return 10000; }
 
 bsm_status bsm_ctx_create(int32_t device, void* stream, bsm_ctx* out) {
+  return bsm_ctx_create_ex(device, stream, nullptr, nullptr, nullptr, out);
+}
+
+bsm_status bsm_ctx_create_ex(int32_t device, void* stream, bsm_alloc_fn alloc_fn, bsm_free_fn free_fn, void* user,
+                             bsm_ctx* out) {
   return guard([&] {
     if (!out) fail(BSM_E_INVALID, "NULL output handle");
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) fail(BSM_E_INVALID, "give both allocator callbacks or neither");
     if (device == -1) {  // host-only: pattern validation, canonicalisation, export
       auto c = std::make_unique<bsm_ctx_s>();
       c->device = -1;
@@ -503,6 +545,10 @@ bsm_status bsm_ctx_create(int32_t device, void* stream, bsm_ctx* out) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
     c->mem.device = device;
+    c->mem.user_alloc = alloc_fn;
+    c->mem.user_free = free_fn;
+    c->mem.user = user;
+    c->mem.stream = &c->stream;
     hip_check(hipSetDevice(device), "hipSetDevice");
     int ncu = 0;
     hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device), "CU count");
@@ -535,10 +581,16 @@ bsm_status bsm_ctx_set_timing(bsm_ctx ctx, int32_t on) {
     if (!ctx) fail(BSM_E_INVALID, "NULL context");
     if (ctx->device < 0) fail(BSM_E_DEVICE, "host-only context");
     set_device(ctx);
-    if (on)
+    if (on) {
       for (hipEvent_t& e : ctx->ev)
         if (!e) hip_check(hipEventCreate(&e), "event");
+      for (hipEvent_t& e : ctx->plan_ev)
+        if (!e) hip_check(hipEventCreate(&e), "event");
+      for (hipEvent_t& e : ctx->exec_ev)
+        if (!e) hip_check(hipEventCreate(&e), "event");
+    }
     std::fill(ctx->launched, ctx->launched + kNumericKernels, 0);
+    ctx->plan_timed = ctx->exec_timed = false;
     ctx->timing = on != 0;
   });
 }
@@ -561,6 +613,25 @@ bsm_status bsm_ctx_launch_times(bsm_ctx ctx, float* ms_out) {
       hip_check(hipEventSynchronize(ctx->ev[2 * k + 1]), "event sync");
       hip_check(hipEventElapsedTime(&ms_out[k], ctx->ev[2 * k], ctx->ev[2 * k + 1]), "elapsed time");
     }
+  });
+}
+
+bsm_status bsm_ctx_phase_times(bsm_ctx ctx, float* ms_out) {
+  return guard([&] {
+    if (!ctx || !ms_out) fail(BSM_E_INVALID, "NULL argument");
+    if (!ctx->timing) fail(BSM_E_INVALID, "timing is off (bsm_ctx_set_timing)");
+    set_device(ctx);
+    auto span = [&](hipEvent_t a, hipEvent_t b, bool on) {
+      float ms = -1.0f;
+      if (!on) return ms;
+      hip_check(hipEventSynchronize(b), "event sync");
+      hip_check(hipEventElapsedTime(&ms, a, b), "elapsed time");
+      return ms;
+    };
+    ms_out[0] = span(ctx->plan_ev[0], ctx->plan_ev[1], ctx->plan_timed);
+    ms_out[1] = span(ctx->plan_ev[1], ctx->plan_ev[2], ctx->plan_timed);
+    ms_out[2] = span(ctx->plan_ev[2], ctx->plan_ev[3], ctx->plan_timed);
+    ms_out[3] = span(ctx->exec_ev[0], ctx->exec_ev[1], ctx->exec_timed);
   });
 }
 
@@ -651,6 +722,7 @@ bsm_status bsm_multiply_plan(bsm_ctx ctx, bsm_pattern A, const double* a_vals, c
     pl->my = o.trans_b ? kColMajor : kRowMajor;
     pl->mo = kRowMajor;
     plan_symbolic(pl.get(), a_vals, a_norms, b_vals, b_norms);
+    if (debug_checks()) check_plan(pl.get());
     *out = pl.release();
   });
 }

@@ -63,20 +63,34 @@ inline bsm_status guard(F&& f) {
 
 // ------------------------------------------------------------ allocator
 
-// Size-bucketed cache of device allocations.  Blocks go back to the cache
-// when their owner is destroyed; because all work of a context is ordered on
-// its stream, a cached block can be handed out again at once.
+// Device memory of a context.  By default a size-bucketed cache of hipMalloc
+// blocks: blocks go back to the cache when their owner is destroyed, and
+// because all work of a context is ordered on its stream, a cached block can
+// be handed out again at once.  With caller callbacks (bsm_ctx_create_ex)
+// every block comes from the caller's allocator and goes back to it when its
+// owner is destroyed, with the context's stream, so a stream-ordered
+// allocator (a caching allocator such as torch's) can reuse it at once.
 struct Allocator {
   int device = 0;
   std::multimap<size_t, void*> free_;
   std::map<void*, size_t> live_;
   size_t cached_bytes = 0;
+  bsm_alloc_fn user_alloc = nullptr;
+  bsm_free_fn user_free = nullptr;
+  void* user = nullptr;
+  const hipStream_t* stream = nullptr;   // the owning context's stream
 
   static size_t round(size_t n) { return (n + 511) & ~size_t(511); }
 
   void* alloc(size_t n) {
     if (n == 0) n = 1;
     n = round(n);
+    if (user_alloc) {
+      void* p = user_alloc(n, device, stream ? (void*)*stream : nullptr, user);
+      if (!p) fail(BSM_E_NOMEM, "the caller's allocator returned no memory for %zu bytes", n);
+      live_[p] = n;
+      return p;
+    }
     auto it = free_.lower_bound(n);
     if (it != free_.end() && it->first <= 2 * n) {
       void* p = it->second;
@@ -103,6 +117,11 @@ struct Allocator {
     if (!p) return;
     auto it = live_.find(p);
     if (it == live_.end()) return;
+    if (user_alloc) {
+      if (user_free) user_free(p, it->second, device, stream ? (void*)*stream : nullptr, user);
+      live_.erase(it);
+      return;
+    }
     free_.emplace(it->second, p);
     cached_bytes += it->second;
     live_.erase(it);
@@ -114,7 +133,10 @@ struct Allocator {
   }
   ~Allocator() {
     release_cache();
-    for (auto& kv : live_) (void)hipFree(kv.first);
+    for (auto& kv : live_) {
+      if (!user_alloc) (void)hipFree(kv.first);
+      else if (user_free) user_free(kv.first, kv.second, device, stream ? (void*)*stream : nullptr, user);
+    }
   }
 };
 
@@ -133,6 +155,14 @@ struct bsm_ctx_s {
   bool timing = false;
   hipEvent_t ev[2 * bsm::kNumericKernels] = {};
   int32_t launched[bsm::kNumericKernels] = {};
+  // phase timing (bsm_ctx_phase_times): plan start, norms done, symbolic
+  // phase done, step lists done; numeric phase start and end
+  hipEvent_t plan_ev[4] = {};
+  hipEvent_t exec_ev[2] = {};
+  bool plan_timed = false, exec_timed = false;
+  void mark(hipEvent_t e) {
+    if (timing && e) hip_check(hipEventRecord(e, stream), "timing event");
+  }
   // pinned host staging for small readbacks
   static constexpr size_t kStaging = 4096;
   void* staging = nullptr;
@@ -144,6 +174,10 @@ struct bsm_ctx_s {
   hipEvent_t join[bsm::kNumericKernels - 1] = {};
   ~bsm_ctx_s() {
     for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : plan_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : exec_ev)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : join)
       if (e) (void)hipEventDestroy(e);
@@ -252,10 +286,11 @@ inline void set_device(bsm_ctx c) {
 
 // Side streams of the numeric launches (default priority, not blocking on the
 // null stream) for a context with concurrent families; P is left alone
-// otherwise.
-inline void attach_side_streams(bsm_ctx c, NumParams& P) {
+// otherwise, and also when they do not exist yet and create is false.
+inline void attach_side_streams(bsm_ctx c, NumParams& P, bool create = true) {
   if (!c->concurrent) return;
   if (!c->fork) {
+    if (!create) return;
     for (auto& s : c->side)
       if (!s) hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "side stream");
     for (auto& e : c->join)
@@ -414,6 +449,8 @@ struct PlanExt {
                     const double* cin, double* out) = 0;
   virtual void grad(bsm_plan pl, double alpha, const double* dc, const double* x, const double* y,
                     double* dx, double* dy) = 0;
+  // true when exec permutes an operand or the output through scratch memory
+  virtual bool remaps() const = 0;
 };
 }  // namespace bsm_host
 
@@ -477,8 +514,22 @@ OpCsr op_csr(bsm_pattern P, bool trans);
 void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, const double* b_vals,
                    const double* b_norms);
 void validate_mm(bsm_pattern A, bsm_pattern B, bsm_pattern C, double eps, const bsm_mm_opts& o);
+// Caller-provided device scratch (the allocation-free execute).
+struct Scratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+// sc: run without allocating, split-precision piece arrays in sc (too small:
+// BSM_E_UNSUPPORTED before any device work).
 void execute(bsm_plan pl, double alpha, const double* x, const double* y, double beta,
-             const double* cin, double* out);
+             const double* cin, double* out, const Scratch* sc = nullptr);
+size_t split_scratch_bytes(bsm_plan pl);
 void execute_grad(bsm_plan pl, int which, double alpha, const double* x, const double* y, double* out);
+// bsm_check.cpp: host-side consistency check of a plan's index arrays
+// (BSM_E_INVALID naming the first inconsistency); debug_checks() is true
+// when the environment variable BSM_DEBUG is set (not "0"), and every new
+// plan is then checked before it is returned.
+void check_plan(bsm_plan pl);
+bool debug_checks();
 
 }  // namespace bsm_host

@@ -578,7 +578,11 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     padvance();
     const int K8 = (int)(w0 >> 48) * 8;
     const int kv = live ? (int)(w1 >> 48) : 0;
-    const auto ra = make_rsrc((const double*)((const char*)X + (w0 & kMask48)), 0x7ffffff8u);
+    // A: from A(r0, k0) to the step's last valid value of the tile's last
+    // row, so that no pair load reads past the block (a pair starting at the
+    // last valid k gets zero for its second value, as past the range)
+    const auto ra = make_rsrc((const double*)((const char*)X + (w0 & kMask48)),
+                              kv > 0 ? (uint32_t)((mt - 1) * K8 + kv * 8) : 0u);
     const auto rb = make_rsrc((const double*)((const char*)Y + (w1 & kMask48)),
                               kv > 0 ? (uint32_t)(kv * N8 - c08) : 0u);
     // A: the lane's k pairs (2 lk, 2 lk + 1) and (8 + 2 lk, 9 + 2 lk), one
@@ -653,7 +657,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     for (int y = 0; y < NJ; ++y) acc[x][y] = Acc{};
   auto epilogue = [&](const double (&cb)[PRE ? NI : 1][PRE ? NJ : 1][PRE ? NE : 1], int pid, int mn, int tile, int tileq,
                       int64_t cout) __attribute__((always_inline)) {
-    const int M = mn & 0xffff, N = mn >> 16;
+    const int M = mn & 0xffff, N = (int)((uint32_t)mn >> 16);   // block edges up to 65535
     const int er0 = (tile & 0xffff) * kTile, ec0 = ((tile >> 16) & 0x7fff) * kTile;
     const int emt = min(kTile, M - er0), ent = min(kTile, N - ec0);
     const ProbPtrs pp = prob<BATCH>(P, pid);

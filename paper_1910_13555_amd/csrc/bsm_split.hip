@@ -247,7 +247,7 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
     for (int y = 0; y < MY; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
   // result element e of lane l: row 4 (l / 16) + e, column l % 16
   auto epilogue = [&](int pid, int mn, int tile, int64_t cout, int64_t cin) __attribute__((always_inline)) {
-    const int M = mn & 0xffff, N = mn >> 16;
+    const int M = mn & 0xffff, N = (int)((uint32_t)mn >> 16);   // block edges up to 65535
     const int er0 = (tile & 0xffff) * kTile, ec0 = ((tile >> 16) & 0x7fff) * kTile;
     const int emt = min(kTile, M - er0), ent = min(kTile, N - ec0);
     const ProbPtrs pp = prob<BATCH>(P, pid);

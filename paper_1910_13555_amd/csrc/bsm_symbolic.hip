@@ -77,7 +77,10 @@ __device__ __forceinline__ void bit_set(uint32_t* bm, int jl) {
 
 // One wavefront per block; lane l accumulates elements l, l+64, ... then the
 // 64 partial sums are combined pairwise (l with l^h for h = 32..1).  Squares
-// and sums are separately rounded (no contraction into fused multiply-add).
+// and sums are separately rounded: the operations are written here, under
+// fp contract(off), and not through helper functions such as __dmul_rn /
+// __dadd_rn, whose bodies are compiled without the pragma and whose multiply
+// and add the backend would fuse into one FMA after inlining.
 __global__ void __launch_bounds__(256) k_block_norms(int64_t nblk, const int64_t* __restrict__ off,
                                                      const double* __restrict__ v,
                                                      double* __restrict__ out) {
@@ -89,10 +92,11 @@ __global__ void __launch_bounds__(256) k_block_norms(int64_t nblk, const int64_t
   double s = 0.0;
   for (int64_t e = l; e < n; e += kWave) {
     const double x = v[base + e];
-    s = __dadd_rn(s, __dmul_rn(x, x));
+    const double q = x * x;
+    s = s + q;
   }
 #pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) s = __dadd_rn(s, __shfl_xor(s, h, kWave));
+  for (int h = 32; h >= 1; h >>= 1) s = s + __shfl_xor(s, h, kWave);
   if (l == 0) out[b] = s;
 }
 
@@ -133,12 +137,15 @@ __global__ void __launch_bounds__(256) k_block_norms2(int64_t na, const int64_t*
     for (int q = 0; q < kNormBlocks; ++q) x[q] = e < len[q] ? v[base[q] + e] : 0.0;
 #pragma unroll
     for (int q = 0; q < kNormBlocks; ++q)
-      if (e < len[q]) s[q] = __dadd_rn(s[q], __dmul_rn(x[q], x[q]));
+      if (e < len[q]) {
+        const double sq = x[q] * x[q];
+        s[q] = s[q] + sq;
+      }
   }
 #pragma unroll
   for (int q = 0; q < kNormBlocks; ++q) {
 #pragma unroll
-    for (int h = 32; h >= 1; h >>= 1) s[q] = __dadd_rn(s[q], __shfl_xor(s[q], h, kWave));
+    for (int h = 32; h >= 1; h >>= 1) s[q] = s[q] + __shfl_xor(s[q], h, kWave);
     if (l == 0 && b0 + q < n) out[b0 + q] = s[q];
   }
 }

@@ -317,6 +317,8 @@ struct ContractExt : PlanExt {
     }
   }
 
+  bool remaps() const override { return r1.on || r2.on || r3out.on; }
+
   void grad(bsm_plan pl, double alpha, const double* dc, const double* x, const double* y, double* dx,
             double* dy) override {
     DBuf<double> sdc, s1, s2, g1, g2;
@@ -608,8 +610,10 @@ bsm_status bsm_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, con
                              double filter_eps, const bsm_mm_opts* opts, bsm_plan* out) {
   return guard([&] {
     if (!ctx || !out) fail(BSM_E_INVALID, "NULL context or output handle");
-    *out = make_contract_plan(ctx, spec, T1, t1_vals, T2, t2_vals, T3_in, filter_eps,
-                              opts ? *opts : kDefaultOpts);
+    std::unique_ptr<bsm_plan_s> pl(make_contract_plan(ctx, spec, T1, t1_vals, T2, t2_vals, T3_in, filter_eps,
+                                                      opts ? *opts : kDefaultOpts));
+    if (debug_checks()) check_plan(pl.get());
+    *out = pl.release();
   });
 }
 

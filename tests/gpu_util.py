@@ -63,10 +63,30 @@ def stack_triples(plan, A, B, trans_a=False, trans_b=False, Cpat=None):
     return sorted(out)
 
 
-def assert_close(got, ref, tol):
+def assert_within(got_blocks, ref_blocks, bound):
+    """Every element within the oracle's elementwise rounding bound
+    ({block: array}); blocks of the bound only (a sample may cover fewer)."""
+    worst = 0.0
+    for key, bd in bound.items():
+        diff = np.abs(np.asarray(got_blocks[key]) - np.asarray(ref_blocks[key]))
+        bad = diff > bd
+        assert not np.any(bad), (f"block {key}: {int(bad.sum())} elements beyond the rounding bound "
+                                 f"(largest excess {float(np.max(diff - bd)):.3e})")
+        pos = bd > 0
+        if np.any(pos):
+            worst = max(worst, float(np.max(diff[pos] / bd[pos])))
+    return worst
+
+
+def assert_close(got, ref, tol, bound=None):
+    """Same pattern, relative Frobenius error <= tol, and, with ``bound``,
+    every element within the oracle's elementwise rounding bound."""
     assert sorted(got.blocks) == sorted(ref.blocks), "patterns differ"
     err = ob.rel_frob_diff(got, ref)
     assert err <= tol, f"relative Frobenius error {err:.3e} > {tol}"
+    if bound is not None:
+        assert sorted(bound) == sorted(ref.blocks)
+        assert_within(got.blocks, ref.blocks, bound)
     return err
 
 
@@ -83,11 +103,13 @@ def tensor_to_oracle(pattern, values, mode_sizes):
     return ot.BlockSparseTensor(mode_sizes, blocks)
 
 
-def assert_tensor_close(got, ref, tol):
-    from oracle import tensor as ot
+def assert_tensor_close(got, ref, tol, bound=None):
     assert sorted(got.blocks) == sorted(ref.blocks), "tensor patterns differ"
     num = sum(float(np.sum((got.blocks[k] - ref.blocks[k]) ** 2)) for k in ref.blocks)
     den = sum(float(np.sum(ref.blocks[k] ** 2)) for k in ref.blocks)
     err = (num / den) ** 0.5 if den > 0 else num ** 0.5
     assert err <= tol, f"relative Frobenius error {err:.3e} > {tol}"
+    if bound is not None:
+        assert sorted(bound) == sorted(ref.blocks)
+        assert_within(got.blocks, ref.blocks, bound)
     return err

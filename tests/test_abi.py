@@ -144,3 +144,20 @@ def test_tuning_table_roundtrip(tmp_path):
         bsm.bsm_tune_load(None)
     assert bsm.bsm_tune_get() == default
     assert bsm.bsm_tune_get_panel() == (0, 0)
+
+
+def test_ctx_create_ex_needs_both_callbacks():
+    """bsm_ctx_create_ex: an allocator callback without its free callback is
+    refused; both on a host-only context are accepted (never called)."""
+    from paper_1910_13555_amd import _lib
+    calls = []
+    alloc = _lib.ALLOC_FN(lambda n, d, s, u: calls.append(n) or None)
+    free = _lib.FREE_FN(lambda p, n, d, s, u: calls.append(-n))
+    h = C.c_void_p()
+    assert _lib.lib.bsm_ctx_create_ex(-1, None, alloc, _lib.FREE_FN(), None, C.byref(h)) == _lib.BSM_E_INVALID
+    assert _lib.lib.bsm_ctx_create_ex(-1, None, alloc, free, None, C.byref(h)) == _lib.BSM_OK
+    st, p, _ = _create(h, [2, 3], [4], [1, 0], [0, 0])
+    assert st == _lib.BSM_OK
+    _lib.check(_lib.lib.bsm_pattern_destroy(p))
+    _lib.check(_lib.lib.bsm_ctx_destroy(h))
+    assert calls == []

@@ -59,10 +59,12 @@ def test_gradient_matches_oracle(bsm, seed):
     ref, trip = ob.multiply(oA, oB, oC, alpha, beta, eps, ta, tb)
     oG = to_oracle(out.pattern, G, ref.row_sizes, ref.col_sizes)
     rdA, rdB, rdC = ob.multiply_backward(oA, oB, oC, oG, trip, alpha, beta, ta, tb)
-    for got_t, M, ref_m in ((A.values.grad, A, rdA), (B.values.grad, B, rdB), (Cm.values.grad, Cm, rdC)):
+    bA, bB, bC = ob.backward_error_bound(oA, oB, oG, trip, alpha, ta, tb, oC, beta)
+    for got_t, M, ref_m, bd in ((A.values.grad, A, rdA, bA), (B.values.grad, B, rdB, bB),
+                                (Cm.values.grad, Cm, rdC, bC)):
         got = to_oracle(M.pattern, got_t, M.row_sizes, M.col_sizes)
         if any(np.any(b != 0) for b in ref_m.blocks.values()):
-            assert_close(got, ref_m, TOL)
+            assert_close(got, ref_m, TOL, bd.blocks)
         else:
             for b in got.blocks.values():
                 assert np.all(b == 0)
@@ -113,8 +115,9 @@ def test_gradient_banded_sampled(bsm):
     ref, trip = ob.multiply(oA, oB, eps=d["eps"])
     oG = to_oracle(plan.c_pattern(), G, ref.row_sizes, ref.col_sizes)
     rdA, rdB, _ = ob.multiply_backward(oA, oB, None, oG, trip)
-    assert_close(to_oracle(A.pattern, da, A.row_sizes, A.col_sizes), rdA, TOL)
-    assert_close(to_oracle(B.pattern, db, B.row_sizes, B.col_sizes), rdB, TOL)
+    bA, bB, _ = ob.backward_error_bound(oA, oB, oG, trip)
+    assert_close(to_oracle(A.pattern, da, A.row_sizes, A.col_sizes), rdA, TOL, bA.blocks)
+    assert_close(to_oracle(B.pattern, db, B.row_sizes, B.col_sizes), rdB, TOL, bB.blocks)
 
 
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True)])
@@ -152,4 +155,5 @@ def test_gradient_split_k(bsm, ta, tb):
     ref, trip = ob.multiply(oA, oB, None, 0.75, 0.0, 0.0, ta, tb)
     oG = to_oracle(out.pattern, G, ref.row_sizes, ref.col_sizes)
     _, rdB, _ = ob.multiply_backward(oA, oB, None, oG, trip, 0.75, 0.0, ta, tb)
-    assert_close(to_oracle(B.pattern, g1, B.row_sizes, B.col_sizes), rdB, TOL)
+    _, bB, _ = ob.backward_error_bound(oA, oB, oG, trip, 0.75, ta, tb)
+    assert_close(to_oracle(B.pattern, g1, B.row_sizes, B.col_sizes), rdB, TOL, bB.blocks)

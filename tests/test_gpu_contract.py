@@ -67,12 +67,14 @@ def test_contract_matches_oracle(bsm, spec, seed):
     T1, T2 = to_lib(bsm, d1), to_lib(bsm, d2)
     T3 = to_lib(bsm, d3) if d3 is not None else None
     R = bsm.contract(spec, T1, T2, T3, alpha, beta, eps)
+    R.plan.check()
     torch.cuda.synchronize()
     ref, pairs = ot.contract(to_ref(d1), to_ref(d2), spec, to_ref(d3) if d3 else None, alpha, beta, eps)
     assert R.plan.info["nprod"] == len(pairs)
     got = tensor_to_oracle(R.pattern, R.values, ref.mode_sizes)
     if ref.blocks:
-        assert_tensor_close(got, ref, TOL)
+        bound = ot.contract_error_bound(to_ref(d1), to_ref(d2), spec, to_ref(d3) if d3 else None, alpha, beta, eps)
+        assert_tensor_close(got, ref, TOL, bound)
 
 
 @pytest.mark.parametrize("spec", SPECS)
@@ -89,10 +91,11 @@ def test_contract_gradient_matches_oracle(bsm, spec):
     ref, pairs = ot.contract(r1, r2, spec, alpha=1.25)
     oG = tensor_to_oracle(R.pattern, G, ref.mode_sizes)
     g1, g2 = ot.contract_backward(r1, r2, spec, oG, pairs, alpha=1.25)
-    for T, g in ((T1, g1), (T2, g2)):
+    b1, b2 = ot.contract_backward_error_bound(r1, r2, spec, oG, pairs, alpha=1.25)
+    for T, g, bd in ((T1, g1, b1), (T2, g2, b2)):
         got = tensor_to_oracle(T.pattern, T.values.grad, T.mode_sizes)
         if any(np.any(b != 0) for b in g.blocks.values()):
-            assert_tensor_close(got, g, TOL)
+            assert_tensor_close(got, g, TOL, bd)
 
 
 def rank3_small(n_mu=30, n_nu=30, n_lam=30, n_p=10, occ=0.05):
@@ -109,7 +112,8 @@ def test_rank3_workload_small(bsm):
     R = bsm.contract("mnP,nl->mlP", to_lib(bsm, T), to_lib(bsm, M))
     ref, pairs = ot.contract(to_ref(T), to_ref(M), "mnP,nl->mlP")
     assert R.plan.info["nprod"] == len(pairs)
-    assert_tensor_close(tensor_to_oracle(R.pattern, R.values, ref.mode_sizes), ref, TOL)
+    assert_tensor_close(tensor_to_oracle(R.pattern, R.values, ref.mode_sizes), ref, TOL,
+                        ot.contract_error_bound(to_ref(T), to_ref(M), "mnP,nl->mlP"))
 
 
 def test_rank3_ten_block_finite_differences(bsm):
@@ -172,7 +176,8 @@ def test_contract_large_tuple_space(bsm):
     torch.cuda.synchronize()
     ref, pairs = ot.contract(to_ref(d1), to_ref(d2), "abc,cd->abd")
     assert R.plan.info["nprod"] == len(pairs)
-    assert_tensor_close(tensor_to_oracle(R.pattern, R.values, ref.mode_sizes), ref, TOL)
+    assert_tensor_close(tensor_to_oracle(R.pattern, R.values, ref.mode_sizes), ref, TOL,
+                        ot.contract_error_bound(to_ref(d1), to_ref(d2), "abc,cd->abd"))
 
 
 def test_chained_output_pattern(bsm):
@@ -199,7 +204,7 @@ def test_chained_output_pattern(bsm):
     got2 = tensor_to_oracle(R2.pattern, R2.values, ref2.mode_sizes)
     assert sorted(got2.blocks) == sorted(ref2.blocks)
     if ref2.blocks:
-        assert_tensor_close(got2, ref2, TOL)
+        assert_tensor_close(got2, ref2, TOL, ot.contract_error_bound(ref1, to_ref(d3), "abd,de->abe"))
 
 
 @pytest.mark.parametrize("variant", [0, 1])
@@ -235,7 +240,8 @@ def test_split_output_rows_both_variants(bsm, variant, with_t3):
     got = tensor_to_oracle(R.pattern, R.values, ref.mode_sizes)
     assert sorted(got.blocks) == sorted(ref.blocks)
     if ref.blocks:
-        assert_tensor_close(got, ref, TOL)
+        assert_tensor_close(got, ref, TOL, ot.contract_error_bound(to_ref(d1), to_ref(d2), "mnP,nl->mlP",
+                                                                   to_ref(d3) if d3 else None, alpha, beta))
     if T3 is not None:
         gr = tensor_to_oracle(R.pattern, g, ref.mode_sizes)
         d3g = tensor_to_oracle(T3.pattern, T3.values.grad, ref.mode_sizes)

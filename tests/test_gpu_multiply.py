@@ -35,6 +35,7 @@ def run(bsm, dA, dB, dC=None, alpha=1.0, beta=0.0, eps=0.0, ta=False, tb=False, 
 def check_against_oracle(bsm, dA, dB, dC=None, alpha=1.0, beta=0.0, eps=0.0, ta=False, tb=False,
                          rs=False):
     A, B, Cm, out = run(bsm, dA, dB, dC, alpha, beta, eps, ta, tb, rs)
+    out.plan.check()
     oA, oB = ob.BlockSparse.from_workload(dA), ob.BlockSparse.from_workload(dB)
     oC = ob.BlockSparse.from_workload(dC) if dC is not None else None
     ref, trip = ob.multiply(oA, oB, oC, alpha, beta, eps, ta, tb, rs)
@@ -42,7 +43,7 @@ def check_against_oracle(bsm, dA, dB, dC=None, alpha=1.0, beta=0.0, eps=0.0, ta=
     assert stack_triples(out.plan, A, B, ta, tb, out.pattern) == sorted(trip)
     assert out.plan.info["flops"] == ob.flop_count(oA, oB, trip, ta, tb)
     if ref.blocks:
-        assert_close(got, ref, TOL)
+        assert_close(got, ref, TOL, ob.multiply_error_bound(oA, oB, oC, alpha, beta, eps, ta, tb, rs))
     return out
 
 
@@ -130,7 +131,8 @@ def sampled_rows_check(bsm, d, nsample, seed):
     got_all = to_oracle(out.pattern, out.values, ref.row_sizes, ref.col_sizes)
     got = ob.BlockSparse(ref.row_sizes, ref.col_sizes,
                          {k: v for k, v in got_all.blocks.items() if k[0] in rows})
-    err = assert_close(got, ref, TOL)
+    bound = ob.multiply_error_bound(oA, oB, oC, d["alpha"], d["beta"], d["eps"], rows=rows)
+    err = assert_close(got, ref, TOL, bound)
     st = [t for t in stack_triples(out.plan, A, B, Cpat=out.pattern) if t[0] in rows]
     assert st == sorted(trip)
     return out, err
@@ -234,6 +236,7 @@ def test_plan_stacks_match_oracle(bsm, seed):
     Cm = bsm.BlockSparseMatrix.from_workload(dC) if dC is not None else None
     plan = bsm.bsm_multiply_plan(A.pattern.ctx, A.pattern, A.values, B.pattern, B.values,
                                  Cm.pattern if Cm else None, eps, retain_sparsity=retain)
+    plan.check()   # host-side check: offsets inside their blocks, one owner per tile
     ref, trip = ob.multiply(oA, oB, oC, 1.0, 0.0, eps, False, False, retain)
     pat = plan.c_pattern()
     rows, cols, _ = pat.export()
@@ -254,3 +257,39 @@ def test_plan_rejects_blocks_of_2gb(bsm):
     A2, _ = bsm.bsm_pattern_create(ctx, [16383], [16384], [0], [0])
     plan = bsm.bsm_multiply_plan(ctx, A2, None, B, None)
     assert plan.info["nprod"] == 1 and plan.info["c_nvals"] == 16383
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_output_blocks_wider_than_32767(bsm, variants, variant):
+    """Output blocks of 40 000 columns: the tile width travels packed with the
+    height in one 32-bit word and must come back unsigned."""
+    variants(variant)
+    rng = np.random.default_rng(88)
+    dA = workloads.random_matrix(rng, np.array([3, 13], np.int32), np.array([5], np.int32), 1.0)
+    dB = workloads.random_matrix(rng, np.array([5], np.int32), np.array([40000, 7], np.int32), 1.0)
+    out = check_against_oracle(bsm, dA, dB, alpha=0.5)
+    assert out.plan.info["c_nvals"] == 16 * 40007
+
+
+def test_odd_k_operand_reads_stay_inside_blocks(bsm):
+    """Inner block sizes 5, 13, 23 (odd): the row-major kernels load A in
+    pairs of k, and the plan check confirms that every step's A range ends
+    at its tile's last valid value, inside the block, also for the last
+    block of A (whose end is the end of the values)."""
+    rng = np.random.default_rng(89)
+    ks = np.array([5, 13, 23, 1, 3], np.int32)
+    rs = np.array([23, 13, 5, 33], np.int32)
+    dA = workloads.random_matrix(rng, rs, ks, 1.0)
+    dB = workloads.random_matrix(rng, ks, np.array([13, 23, 5], np.int32), 1.0)
+    A = bsm.BlockSparseMatrix.from_workload(dA)
+    B = bsm.BlockSparseMatrix.from_workload(dB)
+    # the values end exactly where the last block ends
+    a_exact = A.values[: A.pattern.nvals].clone()
+    plan = bsm.bsm_multiply_plan(A.pattern.ctx, A.pattern, a_exact, B.pattern, B.values)
+    plan.check()
+    out = plan.execute(1.0, a_exact, B.values)
+    torch.cuda.synchronize()
+    oA, oB = ob.BlockSparse.from_workload(dA), ob.BlockSparse.from_workload(dB)
+    ref, _ = ob.multiply(oA, oB)
+    got = to_oracle(plan.c_pattern(), out, ref.row_sizes, ref.col_sizes)
+    assert_close(got, ref, TOL, ob.multiply_error_bound(oA, oB))

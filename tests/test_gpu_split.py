@@ -45,6 +45,7 @@ def run_case(bsm, dA, dB, dC, alpha, beta, eps, scheme):
     ctx = A.pattern.ctx
     plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values,
                                  Cm.pattern if Cm else None, eps, precision=scheme)
+    plan.check()
     out = plan.execute(alpha, A.values, B.values, beta, Cm.values if Cm else None)
     torch.cuda.synchronize()
     oA, oB = ob.BlockSparse.from_workload(dA), ob.BlockSparse.from_workload(dB)
