@@ -97,7 +97,7 @@ def test_every_refused_block_gives_nomem_and_leaks_nothing(bsm, precision):
     for n in range(1, needed + 1):
         probe.fail_at = probe.calls + n
         held = dict(probe.live)
-        out = torch.full((1 << 16,), float("nan"), dtype=torch.float64, device="cuda")
+        out = torch.full((plan.info["c_nvals"],), float("nan"), dtype=torch.float64, device="cuda")
         try:
             pl = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, None, d["eps"],
                                        precision=precision)
