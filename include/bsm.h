@@ -224,6 +224,21 @@ bsm_status bsm_plan_export_stack(bsm_plan plan, int64_t* a_blk, int64_t* b_blk,
 bsm_status bsm_plan_execute(bsm_plan plan, double alpha, const double* a_vals,
                             const double* b_vals, double beta, const double* c_in_vals,
                             double* c_out_vals);
+/* bsm_plan_execute for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): same
+ * arguments, same results bit for bit, and no device allocation.  The only
+ * device memory it needs beyond the caller's buffers -- the bfloat16 piece
+ * arrays of split-precision plans -- comes from one fixed 256 MiB array per
+ * device that the library holds until the process ends; a plan that needs
+ * more, or a contraction plan that permutes an operand or its output through
+ * scratch, is refused with BSM_E_UNSUPPORTED before any device work.  Calls
+ * share that array: calls whose work overlaps on one device (different
+ * streams or contexts) race; calls ordered on one stream do not.  Kernel
+ * families run one after another unless the context's side streams already
+ * exist (an earlier bsm_plan_execute creates them). */
+bsm_status bsm_plan_execute_noalloc(bsm_plan plan, double alpha, const double* a_vals,
+                                    const double* b_vals, double beta, const double* c_in_vals,
+                                    double* c_out_vals);
 /* Plan + execute in one call for an output pattern the caller already knows
  * (retain_sparsity, or C_in covering every product): c_out must hold
  * pat(C_out) = pat(C_in) values; BSM_E_SHAPE if the product would add blocks. */

@@ -266,6 +266,15 @@ class Plan:
                                    _ptr(c_in), _ptr(out)))
         return out
 
+    def execute_noalloc(self, alpha, a_vals, b_vals, beta=0.0, c_in=None, out=None):
+        """bsm_plan_execute_noalloc: the library allocates nothing (``out`` must be given)."""
+        if out is None:
+            raise ValueError("execute_noalloc needs the output buffer")
+        self._check_sizes(a_vals, b_vals, c_in, out)
+        check(lib.bsm_plan_execute_noalloc(self.handle, float(alpha), _ptr(a_vals), _ptr(b_vals), float(beta),
+                                           _ptr(c_in), _ptr(out)))
+        return out
+
     def backward(self, alpha, dc, a_vals, b_vals, da=None, db=None):
         self._check_sizes(a_vals, b_vals, None, dc)
         self._check_sizes(da, db, None, None)

@@ -66,6 +66,7 @@ PROTOTYPES = {
     "bsm_plan_c_pattern": [_vp, C.POINTER(_vp)],
     "bsm_plan_export_stack": [_vp, _i64p, _i64p, _i64p],
     "bsm_plan_execute": [_vp, C.c_double, _dp, _dp, C.c_double, _dp, _dp],
+    "bsm_plan_execute_noalloc": [_vp, C.c_double, _dp, _dp, C.c_double, _dp, _dp],
     "bsm_multiply": [_vp, C.c_double, _vp, _dp, _vp, _dp, C.c_double, _vp, _dp, _dp, C.c_double,
                      C.POINTER(MmOpts)],
     "bsm_plan_backward": [_vp, C.c_double, _dp, _dp, _dp, _dp, _dp],

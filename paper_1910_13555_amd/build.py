@@ -26,7 +26,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include")]
 
 SOURCES = ["bsm_scan.hip", "bsm_symbolic.hip", "bsm_numeric.hip", "bsm_numeric_rm.hip", "bsm_numeric_rmb.hip", "bsm_numeric_gen.hip", "bsm_split.hip", "bsm_order.hip", "bsm_steps.hip",
-           "bsm_backward.hip", "bsm_remap.hip",
+           "bsm_backward.hip", "bsm_remap.hip", "bsm_noalloc.hip",
            "bsm_api.cpp", "bsm_tensor.cpp", "bsm_batch.cpp", "bsm_check.cpp"]
 
 
