@@ -278,6 +278,44 @@ bsm_status bsm_plan_destroy(bsm_plan plan);
  * when it is created, and a failing check fails the creating call. */
 bsm_status bsm_plan_check(bsm_plan plan);
 
+/* ------------------------------------------------------------ other matrix operations
+ * Sec. 2 names, beside the multiply, the sum and the dot product of two
+ * matrices and the transpose and trace of one.  Values are device float64
+ * buffers in each pattern's canonical layout; patterns are host-built.
+ * Results are deterministic (fixed summation orders). */
+/* pat(A) U pat(B) as a new pattern (same block sizes, else BSM_E_SHAPE). */
+bsm_status bsm_add_pattern(bsm_ctx ctx, bsm_pattern A, bsm_pattern B, bsm_pattern* out);
+/* c = alpha * a + beta * b on the blocks of C (block sizes equal to A's and
+ * B's, else BSM_E_SHAPE): alpha*a and beta*b are each rounded and then added
+ * (no fused multiply-add); a block present in one operand only gives that
+ * operand's scaled value, a block in neither gives zeros, and blocks of A or
+ * B outside C are left out.  B may be NULL (then c = alpha * a on C's
+ * blocks: with C a sub-pattern of A this copies A's values into it, which
+ * with bsm_filter_pattern filters a matrix).  c must not alias a or b. */
+bsm_status bsm_add(bsm_ctx ctx, double alpha, bsm_pattern A, const double* a_vals, double beta,
+                   bsm_pattern B, const double* b_vals, bsm_pattern C, double* c_vals);
+/* Transpose: pattern of A^T (block (j,i) for every block (i,j), size vectors
+ * swapped), then its values: block (j,i) of A^T is the transpose of block
+ * (i,j) of A (exact).  at_vals must not alias a_vals; At must be a pattern
+ * made by bsm_transpose_pattern of A (or equal to one; BSM_E_SHAPE
+ * otherwise). */
+bsm_status bsm_transpose_pattern(bsm_ctx ctx, bsm_pattern A, bsm_pattern* out);
+bsm_status bsm_transpose(bsm_ctx ctx, bsm_pattern A, const double* a_vals, bsm_pattern At, double* at_vals);
+/* Trace: sum of the diagonal elements of the diagonal blocks (i,i); row and
+ * column block sizes must be the same vector (BSM_E_SHAPE).  out: device,
+ * one float64, written on the context's stream (no synchronisation). */
+bsm_status bsm_trace(bsm_ctx ctx, bsm_pattern A, const double* a_vals, double* out);
+/* Dot product: sum over the blocks present in both A and B (same block
+ * sizes) of the products of their elements.  out: device, one float64. */
+bsm_status bsm_dot(bsm_ctx ctx, bsm_pattern A, const double* a_vals, bsm_pattern B, const double* b_vals,
+                   double* out);
+/* Filter of a matrix (the paper's filtering of C after a multiply; a
+ * reading): the pattern of A's blocks whose squared norm s(X) (the norm of
+ * the product filter) is not below eps * eps; eps finite and >= 0.  Copy
+ * the kept values with bsm_add(ctx, 1.0, A, a_vals, 0.0, NULL, NULL, kept,
+ * out).  Synchronises the stream once (the kept count sizes the pattern). */
+bsm_status bsm_filter_pattern(bsm_ctx ctx, bsm_pattern A, const double* a_vals, double eps, bsm_pattern* out);
+
 /* ------------------------------------------------------------ batches
  * Many independent multiplies of uneven sizes executed by one persistent
  * launch per kernel size group over a merged work list, ordered by tile class

@@ -27,7 +27,8 @@ __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmu
            "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
            "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
            "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load",
-           "bsm_tune_panel", "bsm_tune_get_panel"]
+           "bsm_tune_panel", "bsm_tune_get_panel", "add", "transpose", "trace", "dot", "filter_blocks",
+           "identity", "sign_iteration"]
 
 
 _live = {"batch": weakref.WeakSet(), "plan": weakref.WeakSet(), "pattern": weakref.WeakSet(),
@@ -610,3 +611,118 @@ def matmul(A: BlockSparseMatrix, B: BlockSparseMatrix, C: BlockSparseMatrix = No
     res = BlockSparseMatrix(plan.c_pattern(), out, rs, cs)
     res.plan = plan
     return res
+
+
+# ------------------------------------------- sum, dot, transpose, trace, filter
+
+def _wrap(pattern_handle, ctx, values, row_sizes, col_sizes):
+    return BlockSparseMatrix(Pattern(ctx, pattern_handle), values, row_sizes, col_sizes)
+
+
+def add(A: BlockSparseMatrix, B: BlockSparseMatrix = None, alpha=1.0, beta=1.0,
+        pattern: Pattern = None) -> BlockSparseMatrix:
+    """alpha*A + beta*B (Sec. 2's sum) on pat(A) U pat(B), or on ``pattern``."""
+    ctx = A.pattern.ctx
+    if pattern is None:
+        if B is None:
+            pattern = A.pattern
+        else:
+            h = C.c_void_p()
+            check(lib.bsm_add_pattern(ctx.handle, A.pattern.handle, B.pattern.handle, C.byref(h)))
+            pattern = Pattern(ctx, h)
+    out = torch.empty(pattern.nvals, dtype=torch.float64, device=A.values.device)
+    check(lib.bsm_add(ctx.handle, float(alpha), A.pattern.handle, _ptr(A.values), float(beta),
+                      B.pattern.handle if B is not None else None, _ptr(B.values) if B is not None else None,
+                      pattern.handle, _ptr(out)))
+    return BlockSparseMatrix(pattern, out, A.row_sizes, A.col_sizes)
+
+
+def transpose(A: BlockSparseMatrix) -> BlockSparseMatrix:
+    ctx = A.pattern.ctx
+    h = C.c_void_p()
+    check(lib.bsm_transpose_pattern(ctx.handle, A.pattern.handle, C.byref(h)))
+    pt = Pattern(ctx, h)
+    out = torch.empty(pt.nvals, dtype=torch.float64, device=A.values.device)
+    check(lib.bsm_transpose(ctx.handle, A.pattern.handle, _ptr(A.values), pt.handle, _ptr(out)))
+    return BlockSparseMatrix(pt, out, A.col_sizes, A.row_sizes)
+
+
+def trace(A: BlockSparseMatrix) -> torch.Tensor:
+    """Trace as a one-element device tensor (no synchronisation)."""
+    out = torch.empty(1, dtype=torch.float64, device=A.values.device)
+    check(lib.bsm_trace(A.pattern.ctx.handle, A.pattern.handle, _ptr(A.values), _ptr(out)))
+    return out
+
+
+def dot(A: BlockSparseMatrix, B: BlockSparseMatrix) -> torch.Tensor:
+    """Frobenius inner product as a one-element device tensor."""
+    out = torch.empty(1, dtype=torch.float64, device=A.values.device)
+    check(lib.bsm_dot(A.pattern.ctx.handle, A.pattern.handle, _ptr(A.values), B.pattern.handle,
+                      _ptr(B.values), _ptr(out)))
+    return out
+
+
+def filter_blocks(A: BlockSparseMatrix, eps: float) -> BlockSparseMatrix:
+    """Blocks of A whose squared norm is not below eps*eps, values kept."""
+    ctx = A.pattern.ctx
+    h = C.c_void_p()
+    check(lib.bsm_filter_pattern(ctx.handle, A.pattern.handle, _ptr(A.values), float(eps), C.byref(h)))
+    return add(A, None, 1.0, 0.0, Pattern(ctx, h))
+
+
+def identity(sizes, device=0, ctx=None) -> BlockSparseMatrix:
+    """Identity with the given block sizes (diagonal blocks only)."""
+    sizes = np.asarray(sizes, np.int32)
+    n = np.arange(len(sizes), dtype=np.int32)
+    vals = np.concatenate([np.eye(int(s)).ravel() for s in sizes]) if len(sizes) else np.zeros(0)
+    return BlockSparseMatrix.from_lists(sizes, sizes, n, n, vals, device, ctx)
+
+
+def _same_pattern(P, Q):
+    if P.nblk != Q.nblk or P.nvals != Q.nvals:
+        return False
+    a, b = P.export(), Q.export()
+    return all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2]))
+
+
+def sign_iteration(A: BlockSparseMatrix, eps=0.0, tol=1e-10, max_iter=100):
+    """Sign matrix of A by the Newton-Schulz iteration X <- X (3I - X X) / 2
+    from X = A / ||A||_F, every product filtered with eps (the sign matrix
+    algorithm of Sec. 2), until ||X_new - X||_F <= tol ||X_new||_F.  Every
+    operation on matrices runs in the library.  With eps = 0 the plans of a
+    step (X.X, the pattern of 3I - X.X, X.(3I - X.X)) are reused while the
+    pattern of X stays the same; with eps > 0 the kept set depends on the
+    values, so they are rebuilt each step.  Returns (X, iterations, last
+    relative change, steps that reused the previous plans)."""
+    ctx = A.pattern.ctx
+    dev = A.values.device.index or 0
+    X = add(A, None, 1.0 / float(dot(A, A).item()) ** 0.5, 0.0)
+    I3 = add(identity(A.row_sizes, dev, ctx), None, 3.0, 0.0)
+    prev = None        # (pattern of X, X.X plan, its output pattern, 3I - X.X pattern, X.Y plan, its output pattern)
+    reused = 0
+    change, it = float("inf"), 0
+    while it < max_iter:
+        if prev is not None and eps == 0.0 and _same_pattern(prev[0], X.pattern):
+            _, p_xx, x2pat, ypat, p_xy, xnpat = prev
+            reused += 1
+        else:
+            p_xx = bsm_multiply_plan(ctx, X.pattern, X.values, X.pattern, X.values, None, eps)
+            x2pat = p_xx.c_pattern()
+            h = C.c_void_p()
+            check(lib.bsm_add_pattern(ctx.handle, I3.pattern.handle, x2pat.handle, C.byref(h)))
+            ypat = Pattern(ctx, h)
+            p_xy = xnpat = None
+        X2 = BlockSparseMatrix(x2pat, p_xx.execute(1.0, X.values, X.values), X.row_sizes, X.col_sizes)
+        Y = add(I3, X2, 1.0, -1.0, ypat)
+        if p_xy is None:
+            p_xy = bsm_multiply_plan(ctx, X.pattern, X.values, ypat, Y.values, None, eps)
+            xnpat = p_xy.c_pattern()
+        Xn = BlockSparseMatrix(xnpat, p_xy.execute(0.5, X.values, Y.values), X.row_sizes, X.col_sizes)
+        D = add(Xn, X, 1.0, -1.0)
+        change = float(dot(D, D).item()) ** 0.5 / max(float(dot(Xn, Xn).item()) ** 0.5, 1e-300)
+        prev = (X.pattern, p_xx, x2pat, ypat, p_xy, xnpat)
+        X = Xn
+        it += 1
+        if change <= tol:
+            break
+    return X, it, change, reused

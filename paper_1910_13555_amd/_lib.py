@@ -73,6 +73,13 @@ PROTOTYPES = {
     "bsm_plan_cin_grad": [_vp, C.c_double, _dp, _dp],
     "bsm_plan_destroy": [_vp],
     "bsm_plan_check": [_vp],
+    "bsm_add_pattern": [_vp, _vp, _vp, C.POINTER(_vp)],
+    "bsm_add": [_vp, C.c_double, _vp, _dp, C.c_double, _vp, _dp, _vp, _dp],
+    "bsm_transpose_pattern": [_vp, _vp, C.POINTER(_vp)],
+    "bsm_transpose": [_vp, _vp, _dp, _vp, _dp],
+    "bsm_trace": [_vp, _vp, _dp, _dp],
+    "bsm_dot": [_vp, _vp, _dp, _vp, _dp, _dp],
+    "bsm_filter_pattern": [_vp, _vp, _dp, C.c_double, C.POINTER(_vp)],
     "bsm_batch_create": [_vp, C.c_int32, C.POINTER(_vp), C.POINTER(_vp)],
     "bsm_batch_execute": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_vp),
                           C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int32],

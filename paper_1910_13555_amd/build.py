@@ -27,7 +27,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 SOURCES = ["bsm_scan.hip", "bsm_symbolic.hip", "bsm_numeric.hip", "bsm_numeric_rm.hip", "bsm_numeric_rmb.hip", "bsm_numeric_gen.hip", "bsm_split.hip", "bsm_order.hip", "bsm_steps.hip",
            "bsm_backward.hip", "bsm_remap.hip", "bsm_noalloc.hip",
-           "bsm_api.cpp", "bsm_tensor.cpp", "bsm_batch.cpp", "bsm_check.cpp"]
+           "bsm_api.cpp", "bsm_tensor.cpp", "bsm_batch.cpp", "bsm_check.cpp", "bsm_ops.hip", "bsm_ops_api.cpp"]
 
 
 def _compile(src: str) -> str:

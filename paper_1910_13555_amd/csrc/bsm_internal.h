@@ -262,6 +262,32 @@ hipError_t launch_bwd_lists(hipStream_t s, const BwdParams& p, bool fill, int64_
                             const int64_t* pptr, int64_t* px, int64_t* py);
 hipError_t launch_cin_grad(hipStream_t s, int64_t nblk, const int64_t* c_off, const int64_t* cin_off,
                            double beta, const double* dc, double* dcin);
+// bsm_ops.hip: sum, transpose, trace and dot product of block-sparse
+// matrices.  A pattern as the kernels see it: CSR rows (ptr, col), the entry
+// of each block in canonical order (row, col), stored index (blk, null:
+// identity) and stored offsets (off).
+struct OpsPattern {
+  int32_t nr = 0;
+  int64_t nblk = 0;
+  const int32_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const int32_t* row = nullptr;
+  const int32_t* blk = nullptr;
+  const int64_t* off = nullptr;
+};
+hipError_t launch_add(hipStream_t s, const OpsPattern& C, const int32_t* rs, const int32_t* cs, double alpha,
+                      const OpsPattern& A, const double* a, double beta, const OpsPattern& B, const double* b,
+                      double* c);
+// Block e of A^T (row trow[e], column tcol[e] of A^T; sizes trs / tcs, offset
+// toff[e]) from A's block at element offset src[e].
+hipError_t launch_transpose(hipStream_t s, int64_t nblk, const int32_t* trow, const int32_t* tcol,
+                            const int32_t* trs, const int32_t* tcs, const int64_t* toff, const int64_t* src,
+                            const double* a, double* at);
+// part: A.nr (trace) / A.nblk (dot) float64 partial sums; out: one float64.
+hipError_t launch_trace(hipStream_t s, const OpsPattern& A, const int32_t* rs, const double* a, double* part,
+                        double* out);
+hipError_t launch_dot(hipStream_t s, const OpsPattern& A, const int32_t* rs, const int32_t* cs, const double* a,
+                      const OpsPattern& B, const double* b, double* part, double* out);
 // bsm_remap.hip: permute the modes of every block (dims: 4 per block, storage
 // order; perm4[a] = storage mode of target mode a).
 hipError_t launch_remap(hipStream_t s, int64_t nblk, const int64_t* off, const int32_t* dims,

@@ -23,6 +23,8 @@ SPECS = [
     "ijk,kjl->il",      # second operand remapped, two summed modes
     "mnP,nl->lmP",      # output remapped
     "iajb,jbc->iac",    # rank 4, two summed modes
+    "iabc,abcj->ij",    # three summed modes, row-major operands
+    "abci,cabj->ji",    # three summed modes, both operands remapped, output transposed
 ]
 
 

@@ -22,7 +22,8 @@ def same_sizes(rng, T, mode, other_sizes):
 
 
 @pytest.mark.parametrize("spec", ["mnP,nl->mlP", "abc,cd->abd", "ab,bc->ac",
-                                  "ijk,jkl->il", "iajb,jbc->iac", "ab,cb->ac"])
+                                  "ijk,jkl->il", "iajb,jbc->iac", "ab,cb->ac",
+                                  "iabc,abcj->ij", "abci,cabj->ji"])
 def test_dense_tensors_equal_einsum(spec):
     rng = np.random.default_rng(len(spec))
     s1, s2, out, con = ot.parse_spec(spec)
@@ -67,11 +68,17 @@ def test_contraction_equals_matricized_product(seed):
         np.testing.assert_allclose(Rm.blocks[k], R.blocks[k], rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("seed", range(4))
+GRAD_SPECS = ["mnP,nl->mlP", "mnP,nl->mlP", "iajb,jbc->iac", "iabc,abcj->ij", "abci,cabj->ji", "ab,cb->ac"]
+
+
+@pytest.mark.parametrize("seed", range(len(GRAD_SPECS)))
 def test_contraction_gradient_exact_fd(seed):
+    """Exact central differences of <G, contract(T, M)> (bilinear, so any
+    step is exact up to rounding) for one, two and three summed indices."""
     rng = np.random.default_rng(70 + seed)
-    spec = "mnP,nl->mlP"
-    nb = dict(m=3, n=3, P=2, l=3)
+    spec = GRAD_SPECS[seed]
+    s1, s2, _, _ = ot.parse_spec(spec)
+    nb = {c: (2 if len(s1) + len(s2) > 6 else 3) for c in set(s1 + s2)}
     sz = {c: rng.choice([1, 2, 3], size=nb[c]) for c in nb}
     def sparse(s, occ):
         T = ot.BlockSparseTensor([sz[c] for c in s])
@@ -79,7 +86,7 @@ def test_contraction_gradient_exact_fd(seed):
             if rng.random() < occ:
                 T.blocks[idx] = rng.uniform(-1, 1, tuple(int(sz[c][i]) for c, i in zip(s, idx)))
         return T
-    T, M = sparse("mnP", 0.5), sparse("nl", 0.6)
+    T, M = sparse(s1, 0.5), sparse(s2, 0.6)
     R, pairs = ot.contract(T, M, spec, alpha=0.7)
     G = ot.BlockSparseTensor(R.mode_sizes, {k: rng.standard_normal(b.shape) for k, b in R.blocks.items()})
     dT, dM = ot.contract_backward(T, M, spec, G, pairs, alpha=0.7)
