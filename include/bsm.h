@@ -309,6 +309,10 @@ bsm_status bsm_trace(bsm_ctx ctx, bsm_pattern A, const double* a_vals, double* o
  * sizes) of the products of their elements.  out: device, one float64. */
 bsm_status bsm_dot(bsm_ctx ctx, bsm_pattern A, const double* a_vals, bsm_pattern B, const double* b_vals,
                    double* out);
+/* y = y + alpha * x over n float64 values (device; x and y may not
+ * overlap unless equal), each product and sum rounded separately; for
+ * accumulating gradients of chunks (bsm_contract_chunks) in a fixed order. */
+bsm_status bsm_axpy(bsm_ctx ctx, int64_t n, double alpha, const double* x, double* y);
 /* Filter of a matrix (the paper's filtering of C after a multiply; a
  * reading): the pattern of A's blocks whose squared norm s(X) (the norm of
  * the product filter) is not below eps * eps; eps finite and >= 0.  Copy
@@ -354,6 +358,31 @@ bsm_status bsm_tpattern_info(bsm_tpattern t, int32_t* rank, int64_t* nblocks, in
 /* Canonical block list: blk_idx (nblocks x rank) and blk_off (host, may be NULL). */
 bsm_status bsm_tpattern_export(bsm_tpattern t, int32_t* blk_idx, int64_t* blk_off);
 bsm_status bsm_tpattern_destroy(bsm_tpattern t);
+
+/* Slice of a tensor pattern along its first mode (the tall dimension of a
+ * contraction, Sec. 4), as a new pattern of context ctx (which may differ
+ * from T's: patterns are host data, so slicing [0, blocks) copies a pattern
+ * into another context, e.g. one per stream): the blocks whose first index
+ * lies in [lo, hi), with the block indices and sizes of T, packed in T's
+ * order; their values are T's values from *val_offset on (host output; may
+ * be NULL), so a slice of a value buffer needs no copy.  BSM_E_UNSUPPORTED if those blocks are not contiguous in
+ * T's packing (they are for patterns made by bsm_tpattern_create, whose
+ * packing is lexicographic, and for contraction outputs whose first mode
+ * leads their matrix rows). */
+bsm_status bsm_tpattern_slice(bsm_ctx ctx, bsm_tpattern T, int32_t lo, int32_t hi, bsm_tpattern* out,
+                              int64_t* val_offset);
+/* Chunks of a contraction along T1's first mode, which must also be the
+ * output's first mode (BSM_E_UNSUPPORTED otherwise): Sec. 4 divides the
+ * largest matrix dimension into smaller submatrices so that tall operands
+ * run in bounded memory.  Each chunk's estimated device memory -- its T1
+ * values twice (the operand and a permuted copy) plus an upper bound of its
+ * output values (every candidate product's output block once), 8 bytes
+ * each -- stays within max_bytes unless one first-mode index alone exceeds
+ * it.  bounds (host, max_chunks + 1 entries) receives the first-mode
+ * boundaries 0 = b_0 < ... < b_n = (blocks of that mode); *nchunks = n.
+ * Contract chunk c with bsm_tpattern_slice(T1, b_c, b_{c+1}) in place of T1. */
+bsm_status bsm_contract_chunks(bsm_ctx ctx, const char* spec, bsm_tpattern T1, bsm_tpattern T2, int64_t max_bytes,
+                               int32_t max_chunks, int32_t* nchunks, int32_t* bounds);
 
 /* Contraction plan (Sec. 4: contraction mapped onto the matrix multiply).
  * spec: einsum-style, e.g. "mnP,nl->mlP": one letter per mode; a letter in

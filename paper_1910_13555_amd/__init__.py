@@ -28,7 +28,7 @@ __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmu
            "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
            "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load",
            "bsm_tune_panel", "bsm_tune_get_panel", "add", "transpose", "trace", "dot", "filter_blocks",
-           "identity", "sign_iteration"]
+           "identity", "sign_iteration", "slice_tensor", "contract_chunks", "contract_chunked"]
 
 
 _live = {"batch": weakref.WeakSet(), "plan": weakref.WeakSet(), "pattern": weakref.WeakSet(),
@@ -538,6 +538,28 @@ def bsm_tpattern_create(ctx: Context, mode_sizes, idx):
     return TensorPattern(ctx, h, sizes), perm
 
 
+def slice_tensor(T, lo, hi):
+    """Blocks of T whose first index lies in [lo, hi): a BlockSparseTensor whose
+    values are a view of T's (no copy)."""
+    h = C.c_void_p()
+    off = np.zeros(1, np.int64)
+    check(lib.bsm_tpattern_slice(T.pattern.ctx.handle, T.pattern.handle, int(lo), int(hi), C.byref(h),
+                                 _lib.as_i64p(off)))
+    pat = TensorPattern(T.pattern.ctx, h, T.mode_sizes)
+    o = int(off[0])
+    return BlockSparseTensor(pat, T.values[o:o + pat.nvals]), o
+
+
+def contract_chunks(spec: str, T1, T2, max_bytes: int, max_chunks: int = 1 << 16):
+    """First-mode boundaries of T1 that split a contraction into chunks of at
+    most about max_bytes of device memory each (bsm_contract_chunks)."""
+    n = C.c_int32()
+    bounds = np.zeros(max_chunks + 1, np.int32)
+    check(lib.bsm_contract_chunks(T1.pattern.ctx.handle, spec.encode(), T1.pattern.handle, T2.pattern.handle,
+                                  int(max_bytes), int(max_chunks), C.byref(n), _lib.as_i32p(bounds)))
+    return bounds[:n.value + 1].tolist()
+
+
 class ContractPlan(Plan):
     def t3_pattern(self, mode_sizes) -> TensorPattern:
         h = C.c_void_p()
@@ -726,3 +748,73 @@ def sign_iteration(A: BlockSparseMatrix, eps=0.0, tol=1e-10, max_iter=100):
         if change <= tol:
             break
     return X, it, change, reused
+
+
+def contract_chunked(spec: str, T1, T2, max_bytes: int, consume, alpha=1.0, filter_eps=0.0, dT1=None, dT2=None,
+                     nstreams: int = 2):
+    """A contraction streamed in chunks along T1's first mode (the tall
+    dimension; Sec. 4 splits it into smaller submatrices), so that outputs
+    larger than the device memory, and the backward, run in bounded memory.
+
+    Chunk c (first-mode range of contract_chunks) is planned and executed on
+    stream c % nstreams, each with its own context, so chunk c + 1's plan and
+    operand permutation overlap chunk c's multiply.  consume(c, R_c, stream)
+    receives the chunk's output tensor (blocks of R whose first index lies in
+    the chunk) while its stream is current; it may return the gradient with
+    respect to R_c's values (a tensor in R_c's layout), which is then
+    propagated: dT1's slice of the chunk is written, and the chunk's
+    gradient of T2 is added into dT2 in chunk order (deterministic).  dT1 /
+    dT2: float64 tensors in T1's / T2's layout, or None.  Returns the chunk
+    bounds."""
+    bounds = contract_chunks(spec, T1, T2, max_bytes)
+    dev = T1.values.device
+    streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
+    ctxs = [Context(dev.index or 0, s.cuda_stream) for s in streams]
+    done = [None] * nstreams         # event: the previous chunk on that stream is finished
+    acc_ev = None                    # event: dT2 holds the sum of the chunks so far
+    lhs, o = spec.replace(" ", "").split("->")
+    s1, s2 = lhs.split(",")
+    out_sizes = [T1.mode_sizes[s1.index(c)] if c in s1 else T2.mode_sizes[s2.index(c)] for c in o]
+    cur = torch.cuda.current_stream(dev)
+    start = torch.cuda.Event()
+    start.record(cur)
+    if dT2 is not None:
+        dT2.zero_()      # (the gradient accumulates from zero)
+    for c in range(len(bounds) - 1):
+        k = c % nstreams
+        st, ctx = streams[k], ctxs[k]
+        with torch.cuda.stream(st):
+            st.wait_event(start)
+            T1c, off = slice_tensor(T1, bounds[c], bounds[c + 1])
+            if T1c.pattern.nblocks == 0:
+                continue
+            p1 = TensorPattern(ctx, _clone_tpattern(ctx, T1c.pattern), T1.mode_sizes)
+            p2 = TensorPattern(ctx, _clone_tpattern(ctx, T2.pattern), T2.mode_sizes)
+            plan = bsm_contract_plan(ctx, spec, p1, T1c.values, p2, T2.values, None, filter_eps)
+            R = plan.execute(alpha, T1c.values, T2.values)
+            Rc = BlockSparseTensor(plan.t3_pattern(out_sizes), R)
+            G = consume(c, Rc, st)
+            if G is not None and (dT1 is not None or dT2 is not None):
+                g2 = torch.empty_like(T2.values) if dT2 is not None else None
+                plan.backward(alpha, G.contiguous(), T1c.values, T2.values,
+                              dT1[off:off + p1.nvals] if dT1 is not None else None, g2)
+                if g2 is not None:       # dT2 += g2, one chunk after the other
+                    if acc_ev is not None:
+                        st.wait_event(acc_ev)
+                    check(lib.bsm_axpy(ctx.handle, dT2.numel(), 1.0, _ptr(g2), _ptr(dT2)))
+                    acc_ev = torch.cuda.Event()
+                    acc_ev.record(st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+            done[k] = ev
+    for ev in done:
+        if ev is not None:
+            cur.wait_event(ev)
+    return bounds
+
+
+def _clone_tpattern(ctx, P):
+    """A copy of a tensor pattern in another context (e.g. of another stream)."""
+    h = C.c_void_p()
+    check(lib.bsm_tpattern_slice(ctx.handle, P.handle, 0, len(P.mode_sizes[0]), C.byref(h), None))
+    return h

@@ -80,6 +80,7 @@ PROTOTYPES = {
     "bsm_trace": [_vp, _vp, _dp, _dp],
     "bsm_dot": [_vp, _vp, _dp, _vp, _dp, _dp],
     "bsm_filter_pattern": [_vp, _vp, _dp, C.c_double, C.POINTER(_vp)],
+    "bsm_axpy": [_vp, C.c_int64, C.c_double, _dp, _dp],
     "bsm_batch_create": [_vp, C.c_int32, C.POINTER(_vp), C.POINTER(_vp)],
     "bsm_batch_execute": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(_vp),
                           C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int32],
@@ -89,6 +90,8 @@ PROTOTYPES = {
     "bsm_tpattern_info": [_vp, _i32p, _i64p, _i64p],
     "bsm_tpattern_export": [_vp, _i32p, _i64p],
     "bsm_tpattern_destroy": [_vp],
+    "bsm_tpattern_slice": [_vp, _vp, C.c_int32, C.c_int32, C.POINTER(_vp), _i64p],
+    "bsm_contract_chunks": [_vp, C.c_char_p, _vp, _vp, C.c_int64, C.c_int32, _i32p, _i32p],
     "bsm_contract_plan": [_vp, C.c_char_p, _vp, _dp, _vp, _dp, _vp, C.c_double,
                           C.POINTER(MmOpts), C.POINTER(_vp)],
     "bsm_plan_t3_pattern": [_vp, C.POINTER(_vp)],

@@ -288,6 +288,7 @@ hipError_t launch_trace(hipStream_t s, const OpsPattern& A, const int32_t* rs, c
                         double* out);
 hipError_t launch_dot(hipStream_t s, const OpsPattern& A, const int32_t* rs, const int32_t* cs, const double* a,
                       const OpsPattern& B, const double* b, double* part, double* out);
+hipError_t launch_axpy(hipStream_t s, int64_t n, double alpha, const double* x, double* y);
 // bsm_remap.hip: permute the modes of every block (dims: 4 per block, storage
 // order; perm4[a] = storage mode of target mode a).
 hipError_t launch_remap(hipStream_t s, int64_t nblk, const int64_t* off, const int32_t* dims,

@@ -143,6 +143,16 @@ __global__ void __launch_bounds__(kOpsThreads) k_sum_parts(int64_t n, const doub
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// y = y + alpha * x, element by element
+__global__ void __launch_bounds__(kOpsThreads) k_axpy(int64_t n, double alpha, const double* __restrict__ x,
+                                                      double* y) {
+#pragma clang fp contract(off)
+  for (int64_t i = (int64_t)blockIdx.x * kOpsThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kOpsThreads) {
+    const double p = alpha * x[i];
+    y[i] = y[i] + p;
+  }
+}
+
 unsigned grid_of(int64_t waves) { return (unsigned)((waves + kOpsWaves - 1) / kOpsWaves); }
 
 }  // namespace
@@ -183,6 +193,13 @@ hipError_t launch_dot(hipStream_t s, const OpsPattern& A, const int32_t* rs, con
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kOpsThreads), 0, s, A.nblk, part, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(hipStream_t s, int64_t n, double alpha, const double* x, double* y) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + kOpsThreads - 1) / kOpsThreads, 8192);
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)blocks), dim3(kOpsThreads), 0, s, n, alpha, x, y);
   return hipGetLastError();
 }
 

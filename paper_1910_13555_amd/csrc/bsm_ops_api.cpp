@@ -139,6 +139,17 @@ bsm_status bsm_dot(bsm_ctx ctx, bsm_pattern A, const double* a, bsm_pattern B, c
   });
 }
 
+bsm_status bsm_axpy(bsm_ctx ctx, int64_t n, double alpha, const double* x, double* y) {
+  return guard([&] {
+    if (!ctx || n < 0) fail(BSM_E_INVALID, "NULL context or negative length");
+    if (n > 0 && (!x || !y)) fail(BSM_E_INVALID, "NULL vector");
+    if (n > 0 && x != y && ((x < y && x + n > y) || (y < x && y + n > x)))
+      fail(BSM_E_INVALID, "x and y overlap");
+    set_device(ctx);
+    hip_check(launch_axpy(ctx->stream, n, alpha, x, y), "axpy");
+  });
+}
+
 bsm_status bsm_filter_pattern(bsm_ctx ctx, bsm_pattern A, const double* a, double eps, bsm_pattern* out) {
   return guard([&] {
     if (!ctx || !A || !out) fail(BSM_E_INVALID, "NULL argument");

@@ -605,6 +605,84 @@ bsm_status bsm_tpattern_destroy(bsm_tpattern t) {
   return guard([&] { delete t; });
 }
 
+bsm_status bsm_tpattern_slice(bsm_ctx ctx, bsm_tpattern T, int32_t lo, int32_t hi, bsm_tpattern* out,
+                              int64_t* val_offset) {
+  return guard([&] {
+    if (!ctx || !T || !out) fail(BSM_E_INVALID, "NULL argument");
+    T->ensure();
+    if (lo < 0 || hi < lo || hi > T->nb[0]) fail(BSM_E_INVALID, "slice [%d, %d) outside the first mode", lo, hi);
+    int64_t b0 = -1, b1 = -1;
+    for (int64_t b = 0; b < T->nblocks; ++b) {
+      const int32_t i = T->idx[b * T->rank];
+      if (i < lo || i >= hi) continue;
+      if (b0 < 0) b0 = b;
+      else if (b != b1) fail(BSM_E_UNSUPPORTED, "the slice's blocks are not contiguous in the packing");
+      b1 = b + 1;
+    }
+    if (b0 < 0) b0 = b1 = 0;
+    auto t = std::make_unique<bsm_tpattern_s>();
+    t->ctx = ctx;
+    t->rank = T->rank;
+    t->nb = T->nb;
+    t->sz = T->sz;
+    t->nblocks = b1 - b0;
+    t->idx.assign(T->idx.begin() + b0 * T->rank, T->idx.begin() + b1 * T->rank);
+    t->off.resize(t->nblocks + 1);
+    for (int64_t b = b0; b <= b1; ++b) t->off[b - b0] = T->off[b] - T->off[b0];
+    t->nvals = t->off[t->nblocks];
+    if (val_offset) *val_offset = T->off[b0];
+    *out = t.release();
+  });
+}
+
+bsm_status bsm_contract_chunks(bsm_ctx ctx, const char* spec, bsm_tpattern T1, bsm_tpattern T2, int64_t max_bytes,
+                               int32_t max_chunks, int32_t* nchunks, int32_t* bounds) {
+  return guard([&] {
+    if (!ctx || !T1 || !T2 || !nchunks || !bounds) fail(BSM_E_INVALID, "NULL argument");
+    if (max_bytes <= 0 || max_chunks < 1) fail(BSM_E_INVALID, "max_bytes and max_chunks must be positive");
+    T1->ensure();
+    T2->ensure();
+    const Spec sp = parse_spec(spec, T1->rank, T2->rank);
+    if (sp.out[0] != sp.s1[0])
+      fail(BSM_E_UNSUPPORTED, "chunks cut the first operand's first mode, which must lead the output");
+    // for every key of summed block indices: the free extent of T2's blocks with that key, summed
+    std::map<Key, int64_t> t2free;
+    for (int64_t b = 0; b < T2->nblocks; ++b) {
+      Key k = {0, 0, 0, 0};
+      int64_t ext = 1;
+      for (size_t c = 0; c < sp.con.size(); ++c) k[c] = T2->idx[b * T2->rank + sp.s2.find(sp.con[c])];
+      for (char c : sp.free2) ext *= T2->bsize(b, (int)sp.s2.find(c));
+      t2free[k] += ext;
+    }
+    // bytes per first-mode index: its T1 values (the operand and a permuted
+    // copy) and an upper bound of its output values (every candidate product's
+    // output block counted once)
+    std::vector<int64_t> bytes(T1->nb[0], 0);
+    for (int64_t b = 0; b < T1->nblocks; ++b) {
+      Key k = {0, 0, 0, 0};
+      int64_t ext = 1;
+      for (size_t c = 0; c < sp.con.size(); ++c) k[c] = T1->idx[b * T1->rank + sp.s1.find(sp.con[c])];
+      for (char c : sp.free1) ext *= T1->bsize(b, (int)sp.s1.find(c));
+      const auto it = t2free.find(k);
+      const int64_t outv = it == t2free.end() ? 0 : ext * it->second;
+      bytes[T1->idx[b * T1->rank]] += 8 * (2 * (T1->off[b + 1] - T1->off[b]) + outv);
+    }
+    int32_t n = 0;
+    bounds[0] = 0;
+    int64_t acc = 0;
+    for (int32_t i = 0; i < T1->nb[0]; ++i) {
+      if (acc > 0 && acc + bytes[i] > max_bytes) {
+        if (n + 1 >= max_chunks) fail(BSM_E_UNSUPPORTED, "more than %d chunks needed", max_chunks);
+        bounds[++n] = i;
+        acc = 0;
+      }
+      acc += bytes[i];
+    }
+    bounds[++n] = T1->nb[0];
+    *nchunks = n;
+  });
+}
+
 bsm_status bsm_contract_plan(bsm_ctx ctx, const char* spec, bsm_tpattern T1, const double* t1_vals,
                              bsm_tpattern T2, const double* t2_vals, bsm_tpattern T3_in,
                              double filter_eps, const bsm_mm_opts* opts, bsm_plan* out) {

@@ -161,3 +161,46 @@ def test_ctx_create_ex_needs_both_callbacks():
     _lib.check(_lib.lib.bsm_pattern_destroy(p))
     _lib.check(_lib.lib.bsm_ctx_destroy(h))
     assert calls == []
+
+
+def test_tensor_slices_and_chunk_bounds_on_host():
+    """bsm_tpattern_slice and bsm_contract_chunks are host computations: on a
+    host-only context the slices of a lexicographic tensor tile it, and the
+    chunk bounds split its first mode within the budget."""
+    from paper_1910_13555_amd import _lib
+    import workloads
+    ctx = _host_ctx()
+    d = workloads.rank3(40, 20, 20, 10, occupancy=0.05, seed_tag=105, values=False)
+    s = d["sizes"]
+
+    def tpat(sizes, idx):
+        arr = (_lib._i32p * len(sizes))(*[_lib.as_i32p(np.ascontiguousarray(x, np.int32)) for x in sizes])
+        nb = np.array([len(x) for x in sizes], np.int32)
+        ix = np.ascontiguousarray(idx, np.int32)
+        h = C.c_void_p()
+        _lib.check(_lib.lib.bsm_tpattern_create(ctx, len(sizes), _lib.as_i32p(nb), arr, len(ix), _lib.as_i32p(ix),
+                                                None, C.byref(h)))
+        return h, sizes, arr
+    T, tsz, tkeep = tpat([s["mu"], s["nu"], s["P"]], d["T_idx"])
+    M, msz, mkeep = tpat([s["nu"], s["lam"]], np.stack([d["M_rows"], d["M_cols"]], 1))
+    n, bounds = C.c_int32(), np.zeros(65, np.int32)
+    _lib.check(_lib.lib.bsm_contract_chunks(ctx, b"mnP,nl->mlP", T, M, 1 << 18, 64, C.byref(n), _lib.as_i32p(bounds)))
+    b = bounds[:n.value + 1]
+    assert n.value >= 2 and b[0] == 0 and b[-1] == 40 and np.all(np.diff(b) > 0)
+    total = C.c_int64()
+    _lib.check(_lib.lib.bsm_tpattern_info(T, None, None, C.byref(total)))
+    pos = 0
+    for lo, hi in zip(b[:-1], b[1:]):
+        h, off, nv = C.c_void_p(), np.zeros(1, np.int64), C.c_int64()
+        _lib.check(_lib.lib.bsm_tpattern_slice(ctx, T, int(lo), int(hi), C.byref(h), _lib.as_i64p(off)))
+        _lib.check(_lib.lib.bsm_tpattern_info(h, None, None, C.byref(nv)))
+        assert off[0] == pos
+        pos += nv.value
+        _lib.check(_lib.lib.bsm_tpattern_destroy(h))
+    assert pos == total.value
+    # the output must lead with the sliced mode
+    assert _lib.lib.bsm_contract_chunks(ctx, b"mnP,nl->lmP", T, M, 1 << 18, 64, C.byref(n),
+                                        _lib.as_i32p(bounds)) == _lib.BSM_E_UNSUPPORTED
+    for h in (T, M):
+        _lib.check(_lib.lib.bsm_tpattern_destroy(h))
+    _lib.check(_lib.lib.bsm_ctx_destroy(ctx))
