@@ -101,23 +101,40 @@ def compulsory_bytes(plan, A, B, beta):
     return 8 * (int(alen[np.unique(a)].sum()) + int(blen[np.unique(b)].sum()) + plan.info["c_nvals"])
 
 
-def cpu_baseline(d, nrows=2000):
-    """The CPU oracle timed on a bounded sample of output block rows (all 2000 by default)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(d, nrows=1000):
+    """The CPU oracle (block loop, numpy/BLAS) timed on a bounded sample of
+    output block rows (every second one by default), with BLAS on all of the
+    host's cores and again on one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import blocksparse as ob
     A = ob.BlockSparse.from_workload(d["A"])
     B = ob.BlockSparse.from_workload(d["B"])
     n = len(d["A"]["row_sizes"])
     rows = set(range(0, n, max(1, n // nrows)))
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        _, trip = ob.multiply(A, B, eps=d["eps"], rows=rows)
-        dt = time.perf_counter() - t0
+    cores = os.cpu_count() or 1
+    res = {}
+    for threads in (cores, 1):
+        with threadpool_limits(threads):
+            t0 = time.perf_counter()
+            _, trip = ob.multiply(A, B, eps=d["eps"], rows=rows)
+            res[threads] = time.perf_counter() - t0
     f = ob.flop_count(A, B, trip)
-    return {"value": f / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+    return {"value": f / res[cores] / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(rows)} of {n} output block rows of the same workload "
                       f"({len(trip)} products, {f / 1e9:.3f} GFLOP), block-loop oracle, "
-                      f"1 thread, {dt:.1f} s"}
+                      f"BLAS on {cores} threads {res[cores]:.1f} s, on 1 thread {res[1]:.1f} s",
+            "single_thread_value": f / res[1] / 1e9, "cpu_model": cpu_model()}
 
 
 def traffic_from_counters(fetch_csv, write_csv, copy_bytes):
@@ -339,11 +356,47 @@ def rank3_section(bsm, reps, stream):
     fb_ms = (time.perf_counter() - t0) * 1e3 / reps
     # the forward is bound by HBM: R written once (beta = 0) and T, M read once
     comp = 8.0 * (out.values.numel() + T.values.numel() + M.values.numel())
-    return {"workload": d["name"], "products": out.plan.info["nprod"], "useful_gflop_forward": F / 1e9,
-            "forward_ms": fwd_ms, "forward_gflops": F / (fwd_ms * 1e-3) / 1e9,
-            "forward_compulsory_gb": comp / 1e9,
-            "forward_hbm_frac": comp / (fwd_ms * 1e-3) / PEAK_HBM,
-            "forward_backward_ms": fb_ms, "forward_backward_gflops": 3 * F / (fb_ms * 1e-3) / 1e9}
+    res = {"workload": d["name"], "products": out.plan.info["nprod"], "useful_gflop_forward": F / 1e9,
+           "forward_ms": fwd_ms, "forward_gflops": F / (fwd_ms * 1e-3) / 1e9,
+           "forward_compulsory_gb": comp / 1e9,
+           "forward_hbm_frac": comp / (fwd_ms * 1e-3) / PEAK_HBM,
+           "forward_backward_ms": fb_ms, "forward_backward_gflops": 3 * F / (fb_ms * 1e-3) / 1e9}
+    del out, g
+    T.values.grad = None
+    M.values.grad = None
+    torch.cuda.empty_cache()
+    res["chunked"] = rank3_chunked(bsm, T, M, F)
+    return res
+
+
+def rank3_chunked(bsm, T, M, F, budget=16 << 30):
+    """The same contraction and its gradient streamed in chunks of the tall
+    first mode under a device-memory budget for each chunk (two chunks in
+    flight on two streams), the library's buffers taken from torch's
+    allocator so that torch's peak statistic covers them: the output is
+    reduced chunk by chunk (<1, R_c>) and never held whole."""
+    import torch
+    Tv, Mv = T.values.detach(), M.values.detach()
+    Tt = bsm.BlockSparseTensor(T.pattern, Tv)
+    Mt = bsm.BlockSparseTensor(M.pattern, Mv)
+    dT, dM = torch.empty_like(Tv), torch.empty_like(Mv)
+    sums = []
+
+    def consume(c, Rc, stream):
+        sums.append(Rc.values.sum())
+        return torch.ones_like(Rc.values)
+
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    t0 = time.perf_counter()
+    bounds = bsm.contract_chunked("mnP,nl->mlP", Tt, Mt, budget, consume, dT1=dT, dT2=dM, allocator="torch")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    peak = torch.cuda.max_memory_allocated() - base
+    return {"chunks": len(bounds) - 1, "budget_gb": budget / 2 ** 30, "forward_backward_ms": ms,
+            "forward_backward_gflops": 3 * F / (ms * 1e-3) / 1e9,
+            "peak_gb_beyond_inputs_and_gradients": peak / 2 ** 30}
 
 
 def main():
@@ -409,22 +462,36 @@ def main():
             ev[1].record(stream)
         return plan, out
 
+    # a 512 MB write before each timed step evicts the 256 MB last-level
+    # cache, which would otherwise hold the 233 MB of A and B from the step
+    # before (the write itself is outside the timed region)
+    evict = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
     for _ in range(args.warmup):
         plan, out = step()
         plan = None
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
-    t0 = time.perf_counter()
+    per_step = []
     plan = None
     for k in range(args.steps):
         plan = None     # the previous step's plan returns its memory to the library's cache
+        evict.fill_(k & 0xff)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         plan, out = step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+        torch.cuda.synchronize()
+        per_step.append((time.perf_counter() - t0) * 1e3)
+    ms_step = sum(per_step) / args.steps
     numeric_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
     info = plan.info
+    # per-phase device times of one more step (library events on its stream)
+    ctx.set_timing(True)
+    evict.fill_(1)
+    plan2, out2 = step()
+    phases = [round(x, 4) for x in ctx.phase_times()]
+    ctx.set_timing(False)
+    del plan2, out2, evict
 
     # numeric phase alone (plan reuse, as in repeated multiplies with a fixed pattern)
     reuse_ms = time_events(lambda: plan.execute(1.0, A.values, B.values, 0.0, None, out), args.steps,
@@ -441,6 +508,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": float(sorted(per_step)[len(per_step) // 2]),
+        "ms_per_step_min": float(min(per_step)),
+        "phase_ms": {"norms": phases[0], "symbolic": phases[1], "step_lists": phases[2], "numeric": phases[3]},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -751,7 +751,7 @@ def sign_iteration(A: BlockSparseMatrix, eps=0.0, tol=1e-10, max_iter=100):
 
 
 def contract_chunked(spec: str, T1, T2, max_bytes: int, consume, alpha=1.0, filter_eps=0.0, dT1=None, dT2=None,
-                     nstreams: int = 2):
+                     nstreams: int = 2, allocator=None):
     """A contraction streamed in chunks along T1's first mode (the tall
     dimension; Sec. 4 splits it into smaller submatrices), so that outputs
     larger than the device memory, and the backward, run in bounded memory.
@@ -764,12 +764,13 @@ def contract_chunked(spec: str, T1, T2, max_bytes: int, consume, alpha=1.0, filt
     respect to R_c's values (a tensor in R_c's layout), which is then
     propagated: dT1's slice of the chunk is written, and the chunk's
     gradient of T2 is added into dT2 in chunk order (deterministic).  dT1 /
-    dT2: float64 tensors in T1's / T2's layout, or None.  Returns the chunk
-    bounds."""
+    dT2: float64 tensors in T1's / T2's layout, or None.  allocator: that of
+    the chunks' contexts (see Context; "torch" makes torch's memory
+    statistics cover the library's buffers too).  Returns the chunk bounds."""
     bounds = contract_chunks(spec, T1, T2, max_bytes)
     dev = T1.values.device
     streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
-    ctxs = [Context(dev.index or 0, s.cuda_stream) for s in streams]
+    ctxs = [Context(dev.index or 0, s.cuda_stream, allocator) for s in streams]
     done = [None] * nstreams         # event: the previous chunk on that stream is finished
     acc_ev = None                    # event: dT2 holds the sum of the chunks so far
     lhs, o = spec.replace(" ", "").split("->")

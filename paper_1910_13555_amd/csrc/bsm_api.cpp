@@ -78,6 +78,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
   P.cs = tb ? B->d_rs.p : B->d_cs.p;
   P.eps2 = pl->eps * pl->eps;
   P.retain = pl->opts.retain_sparsity;
+  P.stepk = step_k_len(pl->opts.precision != BSM_PREC_FP64);
   ctx->mark(ctx->plan_ev[0]);
   if (C) {
     P.cin_ptr = C->d_ptr.p;
@@ -187,7 +188,7 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     if (pl->nsteps >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 product steps");
     DBuf<int64_t> ch(ctx, pl->nprod + 1), chs(ctx, pl->nprod + 2), ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1);
     DBuf<int32_t> b2t(ctx, pl->c_nblk);
-    hip_check(launch_product_chunks(st, pl->nprod, pl->px.p, ch.p), "product chunks");
+    hip_check(launch_product_chunks(st, pl->nprod, pl->px.p, split, ch.p), "product chunks");
     DBuf<int64_t> scr1(ctx, scan_scratch_size(1, std::max<int64_t>(pl->nprod, 1)));
     hip_check(launch_scan(st, 1, pl->nprod, ch.p, chs.p, nullptr, scr1.p), "chunk scan");
     hip_check(launch_tile_steps(st, (int32_t)pl->ntasks, pl->c_nblk, pl->tasks.p, pl->pptr.p, chs.p, pl->c_row.p,

@@ -182,9 +182,10 @@ void check_plan(bsm_plan pl) {
         const int64_t xb = split ? apad[pa[q]] : pl->A->h_off[pa[q]];
         const int64_t yb = split ? bpad[pb[q]] : pl->B->h_off[pb[q]];
         const uint64_t esz = split ? 2u : 8u;
-        for (int k0 = 0; k0 < K; k0 += 16, ++s) {
+        const int L = step_k_len(split);
+        for (int k0 = 0; k0 < K; k0 += L, ++s) {
           if (s >= d.pbeg + d.np) bad("plan check: work item %lld has too few steps", (long long)w);
-          const uint64_t kv = (uint64_t)std::min(16, K - k0);
+          const uint64_t kv = (uint64_t)std::min(L, K - k0);
           const uint64_t w0 = ((uint64_t)(xb + (int64_t)r0 * Kp + k0) * esz) | ((uint64_t)Kp << 48);
           const uint64_t w1 = (split ? (uint64_t)(yb + (int64_t)c0 * Kp + k0) * esz
                                      : (uint64_t)(yb + (int64_t)k0 * N + c0) * esz) | (kv << 48);

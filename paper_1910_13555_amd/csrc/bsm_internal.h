@@ -20,6 +20,13 @@ constexpr int kSymFields = 7 + kClasses;      // per-row counts of the symbolic 
 // Tile class of an mt x nt tile (1..32 each): (ceil(mt/8)-1)*4 + ceil(nt/8)-1.
 __host__ __device__ inline int tile_class(int mt, int nt) { return ((mt + 7) / 8 - 1) * 4 + ((nt + 7) / 8 - 1); }
 constexpr uint64_t kMask48 = (uint64_t(1) << 48) - 1;
+// k per step record of the row-major numeric path: 16 for float64 plans
+// (four k-steps of the float64 matrix-core instructions; steps of 8 were
+// measured slower on the banded workload: fewer wasted operand loads, but
+// twice the per-step work), 16 for split precision (a pair of steps feeds
+// one 16x16x32 bfloat16 instruction).
+constexpr int kStepK64 = 16, kStepKSplit = 16;
+__host__ __device__ inline int step_k_len(bool split) { return split ? kStepKSplit : kStepK64; }
 
 // Element layout of one block operand, seen as a logical R x C matrix.
 enum Mode : int32_t {
@@ -49,6 +56,7 @@ struct SymParams {
   const int32_t* cs = nullptr;    // op(B) column sizes (nc)
   double eps2 = 0.0;
   int32_t retain = 0;
+  int32_t stepk = kStepK64;       // k per step record (step_k_len of the plan)
 };
 
 // Symbolic count fields (k_sym_count, then prefix sums); field kFClass + c
@@ -170,7 +178,7 @@ hipError_t launch_panel_order(hipStream_t s, int32_t ntiles, int2* tiles, const 
 // Product-parallel step building: chunks per product; per-tile step counts
 // (and the single-tile block map); work items, empty-tile steps and steps of
 // multi-tile blocks; steps of single-tile blocks per product.
-hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, int64_t* chunks);
+hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, bool split, int64_t* chunks);
 // Split precision: the padded piece layout of both operands -- element
 // offsets of their stored blocks (ascending, n + 1 entries) and the offsets
 // of the same blocks in the piece arrays.  Null apad: a float64 plan.

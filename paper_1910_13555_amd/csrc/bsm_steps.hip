@@ -1,11 +1,12 @@
 // Step lists of the row-major numeric path.  A step is one product's k range
-// [k0, k0 + 16) for one output tile; its record holds everything the kernel
+// [k0, k0 + L) for one output tile (L = step_k_len: 8 for float64 plans, 16
+// for split precision); its record holds everything the kernel
 // needs to address that step's operands, so the kernel's per-step work is a
 // few scalar instructions (Sec. 2's stacks, expanded to the granularity of
 // the matrix-core k-steps):
 //   w0 = byte offset of A(r0, k0) in the A values | K << 48
 //   w1 = byte offset of B(k0, c0) in the B values | kv << 48
-// with (r0, c0) the tile's origin in its output block and kv = min(16, K - k0)
+// with (r0, c0) the tile's origin in its output block and kv = min(L, K - k0)
 // the step's valid k.  A tile without products has one step with kv = 0 (its
 // output is beta * C_in).  One work item per tile: pbeg / np give its steps.
 // Split-precision plans pair the steps of a tile (one bfloat16 instruction
@@ -16,8 +17,6 @@
 namespace bsm {
 
 namespace {
-
-constexpr int kStepK = 16;
 
 // Split precision: the block whose element offset is o (off ascending, the
 // block starts; n blocks), i.e. the last s with off[s] <= o.
@@ -49,7 +48,7 @@ __device__ __forceinline__ void product_bases(int64_t xo, int64_t yo, const Piec
 // of B at c * Kp + k) and Kp.
 __device__ __forceinline__ void step_words(int64_t xb, int64_t yb, int K, int N, int r0, int c0, int k0,
                                            bool split, uint64_t* out) {
-  const uint64_t kv = (uint64_t)min(kStepK, K - k0);
+  const uint64_t kv = (uint64_t)min(step_k_len(split), K - k0);
   if (!split) {
     out[0] = ((uint64_t)(xb + (int64_t)r0 * K + k0) * 8u) | ((uint64_t)K << 48);
     out[1] = ((uint64_t)(yb + (int64_t)k0 * N + c0) * 8u) | (kv << 48);
@@ -60,12 +59,12 @@ __device__ __forceinline__ void step_words(int64_t xb, int64_t yb, int K, int N,
   }
 }
 
-// Product-parallel form.  chunks[p] = ceil(K_p / 16) for every product.
-__global__ void k_product_chunks(int64_t nprod, const int64_t* __restrict__ px, int64_t* __restrict__ chunks) {
+// Product-parallel form.  chunks[p] = ceil(K_p / L) for every product.
+__global__ void k_product_chunks(int64_t nprod, const int64_t* __restrict__ px, int L, int64_t* __restrict__ chunks) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprod) return;
   const int K = (int)((uint64_t)px[p] >> 48);
-  chunks[p] = (K + kStepK - 1) / kStepK;
+  chunks[p] = (K + L - 1) / L;
 }
 
 // Per tile: step count from the product chunk prefix (chs, exclusive, nprod + 1
@@ -131,7 +130,8 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
     int64_t xb, yb;
     product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
     const int K = (int)(xw >> 48);
-    for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xb, yb, K, N, r0, c0, k0, pm.apad != nullptr, steps + 2 * s);
+    for (int k0 = 0; k0 < K; k0 += step_k_len(pm.apad != nullptr), ++s)
+      step_words(xb, yb, K, N, r0, c0, k0, pm.apad != nullptr, steps + 2 * s);
   }
 }
 
@@ -153,7 +153,8 @@ __global__ void k_product_steps(int64_t nprod, const int32_t* __restrict__ pblk,
   int64_t xb, yb;
   product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
   const int K = (int)(xw >> 48);
-  for (int k0 = 0; k0 < K; k0 += kStepK, ++s) step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
+  for (int k0 = 0; k0 < K; k0 += step_k_len(pm.apad != nullptr), ++s)
+    step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -163,9 +164,10 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 }  // namespace
 
-hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, int64_t* chunks) {
+hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, bool split, int64_t* chunks) {
   if (nprod == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_product_chunks, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, px, chunks);
+  hipLaunchKernelGGL(k_product_chunks, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, px,
+                     step_k_len(split), chunks);
   return hipGetLastError();
 }
 

@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(kSymThreads) k_sym_count(SymParams P, int64_t*
       if (!c.keep || (P.retain && !bit_test(S.cm, c.j - jlo))) return;
       ++nprod;
       flops += 2 * (int64_t)m * P.ks[c.k] * P.cs[c.j];
-      nsteps += (int64_t)((P.ks[c.k] + 15) / 16) * num_tiles(m, P.cs[c.j]);
+      nsteps += (int64_t)((P.ks[c.k] + P.stepk - 1) / P.stepk) * num_tiles(m, P.cs[c.j]);
       bit_set(S.bm, c.j - jlo);
     });
     if (tid < kSymWords && tid * 32 < jhi - jlo) {
