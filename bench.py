@@ -372,31 +372,34 @@ def rank3_section(bsm, reps, stream):
 def rank3_chunked(bsm, T, M, F, budget=16 << 30):
     """The same contraction and its gradient streamed in chunks of the tall
     first mode under a device-memory budget for each chunk (two chunks in
-    flight on two streams), the library's buffers taken from torch's
-    allocator so that torch's peak statistic covers them: the output is
-    reduced chunk by chunk (<1, R_c>) and never held whole."""
+    flight on two streams): each chunk's output is reduced (<1, R_c>) and
+    its gradient (ones) handed back, so R is never held whole.  The device
+    memory in use beyond the inputs and their gradients is sampled (free
+    memory) at every chunk; the second of two runs is timed."""
     import torch
     Tv, Mv = T.values.detach(), M.values.detach()
     Tt = bsm.BlockSparseTensor(T.pattern, Tv)
     Mt = bsm.BlockSparseTensor(M.pattern, Mv)
     dT, dM = torch.empty_like(Tv), torch.empty_like(Mv)
-    sums = []
+    used = []
 
     def consume(c, Rc, stream):
-        sums.append(Rc.values.sum())
+        used.append(free0 - torch.cuda.mem_get_info()[0])
+        Rc.values.sum()
         return torch.ones_like(Rc.values)
 
-    torch.cuda.synchronize()
-    torch.cuda.reset_peak_memory_stats()
-    base = torch.cuda.memory_allocated()
-    t0 = time.perf_counter()
-    bounds = bsm.contract_chunked("mnP,nl->mlP", Tt, Mt, budget, consume, dT1=dT, dT2=dM, allocator="torch")
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    peak = torch.cuda.max_memory_allocated() - base
+    for _ in range(2):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free0 = torch.cuda.mem_get_info()[0]
+        used.clear()
+        t0 = time.perf_counter()
+        bounds = bsm.contract_chunked("mnP,nl->mlP", Tt, Mt, budget, consume, dT1=dT, dT2=dM)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
     return {"chunks": len(bounds) - 1, "budget_gb": budget / 2 ** 30, "forward_backward_ms": ms,
             "forward_backward_gflops": 3 * F / (ms * 1e-3) / 1e9,
-            "peak_gb_beyond_inputs_and_gradients": peak / 2 ** 30}
+            "max_gb_in_use_beyond_inputs_and_gradients": max(used) / 2 ** 30}
 
 
 def main():
@@ -542,6 +545,7 @@ def main():
         try:
             res["rank3"] = rank3_section(bsm, 3, stream)
             res["rank3"]["tuning"] = bsm.bsm_tune_get()
+            res["rank3"]["run"] = bsm.bsm_tune_get_run()
         except (RuntimeError, MemoryError) as e:   # reported, not fatal to the main line
             res["rank3"] = {"error": str(e)[:300]}
         torch.cuda.empty_cache()

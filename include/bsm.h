@@ -425,6 +425,16 @@ bsm_status bsm_tune_load(const char* path);
  * size 0.  bsm_tune_load also reads an optional "panel": [rows, cols]. */
 bsm_status bsm_tune_panel(int32_t rows, int32_t cols);
 bsm_status bsm_tune_get_panel(int32_t* rows, int32_t* cols);
+/* Work order of the float64 numeric kernels of row-major plans: each
+ * wavefront takes runs of `run` consecutive output tiles of its XCD's share
+ * (neighbours in the output, whose operand blocks overlap, then meet in one
+ * compute unit's L1), the wavefronts of an XCD taking the runs cyclically;
+ * run = 1 (the default) deals single tiles cyclically.  Read at each
+ * execute; results are bit-identical for every run length.  1..4096, else
+ * BSM_E_INVALID.  bsm_tune_load also reads an optional "run": R (and resets
+ * it to 1 without one). */
+bsm_status bsm_tune_run(int32_t run);
+bsm_status bsm_tune_get_run(int32_t* run);
 /* Current table: out16[c] = variant of class c (host array of 16). */
 bsm_status bsm_tune_get(int32_t* out16);
 /* Replace the table (host array of 16 values in {0, 1}; else BSM_E_INVALID).

@@ -19,6 +19,8 @@ extern const bsm_mm_opts kDefaultOpts;
 const bsm_mm_opts kDefaultOpts = {0, 0, 0, BSM_PREC_FP64};
 // Output panel (block rows x block columns) of the numeric work order; 0: canonical order.
 int32_t g_panel[2] = {0, 0};
+// Consecutive tiles per wavefront run on the row-major path (bsm_tune_run).
+int32_t g_run = 1;
 
 // Work items of the numeric kernel from a tile list: one per (tile, segment
 // of <= 64 products), written on the device; `seg` ends with their count.
@@ -311,6 +313,7 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
     P.seg = nullptr;
     P.steps = pl->steps.p;
     P.xb = pl->xb.p;
+    P.run = g_run;
   }
   std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
@@ -912,6 +915,32 @@ bsm_status bsm_tune_load(const char* path) {
     }
     g_panel[0] = panel[0];
     g_panel[1] = panel[1];
+    int32_t run = 1;
+    if (path) {
+      const size_t rk = text.find("\"run\"");
+      const size_t rc = rk == std::string::npos ? rk : text.find(':', rk);
+      if (rc != std::string::npos) {
+        char* end = nullptr;
+        const long x = std::strtol(text.c_str() + rc + 1, &end, 10);
+        if (end == text.c_str() + rc + 1 || x < 1 || x > 4096) fail(BSM_E_INVALID, "%s: \"run\" needs 1..4096", path);
+        run = (int32_t)x;
+      }
+    }
+    g_run = run;
+  });
+}
+
+bsm_status bsm_tune_run(int32_t run) {
+  return guard([&] {
+    if (run < 1 || run > 4096) fail(BSM_E_INVALID, "run length must be 1..4096");
+    g_run = run;
+  });
+}
+
+bsm_status bsm_tune_get_run(int32_t* run) {
+  return guard([&] {
+    if (!run) fail(BSM_E_INVALID, "NULL output");
+    *run = g_run;
   });
 }
 

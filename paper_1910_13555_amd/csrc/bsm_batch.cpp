@@ -196,6 +196,7 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   std::copy(b->cls_tile, b->cls_tile + kClasses + 1, P.cls_tile);
   P.ptab = b->ptab.p;
   P.xb = b->xb.p;
+  P.run = g_run;
   for (int32_t p = 0; p < n; ++p) P.has_cin |= (t[p].beta != 0.0 && t[p].cin != nullptr) ? 1 : 0;
   P.ncu = ctx->ncu;
   P.mx = b->mx;

@@ -117,6 +117,7 @@ struct NumParams {
   int32_t has_cin = 0;            // batches: some problem adds beta * C_in
   uint32_t xpb = 0, ypb = 0;      // split precision: X / Y are piece arrays of this many bytes each
   const int32_t* xb = nullptr;    // row-major path: XCD share bounds, 9 per class (launch_xcd_bounds)
+  int32_t run = 1;                // row-major path: consecutive tiles per wavefront run (work order)
   double* part = nullptr;         // generic path, split-K: kTile * kTile partial sums per work item
   hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
   int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran

@@ -456,9 +456,20 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
 // accumulates the transposed tile and a lane's values lie along the rows of
 // the output -- used for outputs in split rows, whose consecutive rows are
 // adjacent in memory (columns otherwise).
+// Work order: the wavefront owns runs of P.run consecutive tiles of its XCD
+// share -- runs r, r + stride, r + 2 stride, ... -- so that the tiles of a
+// run, neighbours in the output (same block row, next columns: the same
+// rows of A), follow each other on one wavefront and find their shared
+// operand blocks in its compute unit's L1 (runs of 1: the XCD's wavefronts
+// take the share's tiles cyclically).
 template <int V, int NI, int NJ, bool CIN, bool BATCH, int D, bool TR>
 __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, int r, int stride) {
   const int l = threadIdx.x;
+  const int RL = P.run > 0 ? P.run : 1;
+  auto next_tile = [&](int t) __attribute__((always_inline)) {
+    const int q = t - e0;
+    return (q + 1) % RL ? t + 1 : t + 1 + (stride - 1) * RL;
+  };
   const int lrA = V == 0 ? 4 * ((l >> 3) & 1) + (l & 3) : (l & 15);   // row inside an instruction tile
   const int lcB = V == 0 ? 4 * ((l >> 2) & 1) + (l & 3) : (l & 15);   // column inside an instruction tile
   const int lk = l >> 4;                                               // k inside an instruction k-step
@@ -466,18 +477,18 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   constexpr int NE = V == 0 ? 1 : 4;
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-  int it = e0 + r;
+  int it = e0 + r * RL;
   if (it >= e1) return;
 
   // ---- record cursor: walks the wavefront's steps D ahead of the issue
-  // cursor (tile pt, step ps of [ps, pe), descriptor of tile pt + stride
-  // one tile ahead)
+  // cursor (tile pt, step ps of [ps, pe), descriptor of the wavefront's
+  // next tile one tile ahead)
   TaskDesc pdn = desc_at(P, it);
   int pt = it, ps = (int)pdn.pbeg, pe = ps + pdn.np;
   const uint64_t* psteps = BATCH ? prob<BATCH>(P, pdn.pid).steps : P.steps;
   const uint64_t* const first_rec = psteps + 2 * (int64_t)ps;   // a valid address for past-the-end loads
   bool plive = true;
-  if (pt + stride < e1) pdn = desc_at(P, pt + stride);
+  if (next_tile(pt) < e1) pdn = desc_at(P, next_tile(pt));
   auto load_rec = [&]() __attribute__((always_inline)) {
     const uint64_t* q = plive ? psteps + 2 * (int64_t)ps : first_rec;
     return *cptr(reinterpret_cast<const u32x4*>(q));
@@ -485,7 +496,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   auto padvance = [&]() __attribute__((always_inline)) {
     if (!plive) return;
     if (++ps < pe) return;
-    pt += stride;
+    pt = next_tile(pt);
     if (pt >= e1) {
       plive = false;
       return;
@@ -493,13 +504,13 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     if (BATCH) psteps = prob<BATCH>(P, pdn.pid).steps;
     ps = (int)pdn.pbeg;
     pe = ps + pdn.np;
-    if (pt + stride < e1) pdn = desc_at(P, pt + stride);
+    if (next_tile(pt) < e1) pdn = desc_at(P, next_tile(pt));
   };
 
   // ---- issue cursor: tile it (descriptor id), step s of [s, se)
   TaskDesc id = desc_at(P, it);
-  TaskDesc nd = id;                        // descriptor of tile it + stride
-  if (it + stride < e1) nd = desc_at(P, it + stride);
+  TaskDesc nd = id;                        // descriptor of the wavefront's next tile
+  if (next_tile(it) < e1) nd = desc_at(P, next_tile(it));
   int s = (int)id.pbeg, se = s + id.np;
   const double* X = nullptr;
   const double* Y = nullptr;
@@ -640,13 +651,13 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     cout = id.cout;
     if (!live) return;
     if (++s < se) return;
-    it += stride;
+    it = next_tile(it);
     if (it >= e1) return;
     id = nd;
     s = (int)id.pbeg;
     se = s + id.np;
     enter(id);
-    if (it + stride < e1) nd = desc_at(P, it + stride);
+    if (next_tile(it) < e1) nd = desc_at(P, next_tile(it));
   };
 
   using Acc = typename std::conditional<V == 0, double, f64x4>::type;

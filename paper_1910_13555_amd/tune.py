@@ -1,9 +1,10 @@
 """Autotuner of the numeric phase: picks, per output tile class, the
-matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4), then the output
-panel of the work order, that run a workload fastest, by timing the numeric
-phase on the GPU (coordinate descent over the 16 classes starting from the
-built-in table, then a scan of panel edges), and writes the result as JSON
-for bsm_tune_load.
+matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4), then the run length
+of the work order (consecutive tiles per wavefront), then the output panel
+of the work order, that run a workload fastest, by timing the numeric phase
+on the GPU (coordinate descent over the 16 classes starting from the
+built-in table, then scans of run lengths and panel edges), and writes the
+result as JSON for bsm_tune_load.
 
 Usage: python -m paper_1910_13555_amd.tune [--workload banded|batched|tall_skinny|rank3]
                                            [--out FILE] [--reps N]
@@ -91,6 +92,15 @@ def tune(workload="banded", reps=10, min_gain=0.02):
         if t < best * (1.0 - min_gain):
             table, best = trial, t
     bsm.bsm_tune_set(table)
+    # run length: read at execute time, so the same plans serve every trial
+    run = 1
+    for r in (2, 4, 8, 16, 32):
+        bsm.bsm_tune_run(r)
+        t = _time(fn, reps)
+        trials.append({"run": r, "ms": t})
+        if t < best * (1.0 - min_gain):
+            run, best = r, t
+    bsm.bsm_tune_run(run)
     del keep, fn
     # work order: output panel edge (plans are rebuilt, the order is fixed at plan time;
     # not scanned for the rank-3 contraction, whose inputs take minutes to regenerate)
@@ -104,7 +114,7 @@ def tune(workload="banded", reps=10, min_gain=0.02):
         if t < best * (1.0 - min_gain):
             panel, best = (edge, edge), t
     bsm.bsm_tune_panel(*panel)
-    return {"workload": workload, "variant": table, "panel": list(panel), "default_ms": start,
+    return {"workload": workload, "variant": table, "run": run, "panel": list(panel), "default_ms": start,
             "tuned_ms": best, "trials": trials}
 
 
@@ -120,7 +130,7 @@ def main():
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
-    print(json.dumps({k: res[k] for k in ("workload", "variant", "panel", "default_ms", "tuned_ms")}), flush=True)
+    print(json.dumps({k: res[k] for k in ("workload", "variant", "run", "panel", "default_ms", "tuned_ms")}), flush=True)
 
 
 if __name__ == "__main__":

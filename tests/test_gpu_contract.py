@@ -249,3 +249,20 @@ def test_split_output_rows_both_variants(bsm, variant, with_t3):
         d3g = tensor_to_oracle(T3.pattern, T3.values.grad, ref.mode_sizes)
         for k, blk in d3g.blocks.items():
             np.testing.assert_array_equal(blk, beta * gr.blocks[k])
+
+
+def test_split_output_rows_run_lengths_bit_identical(bsm):
+    """The split-row output epilogue under runs of consecutive tiles: the
+    reduced rank-3 contraction is bit-identical for every run length."""
+    T, M = rank3_small(40, 30, 30, 12, 0.05)
+    Tl, Ml = to_lib(bsm, T), to_lib(bsm, M)
+    outs = []
+    try:
+        for run in (1, 3, 16):
+            bsm.bsm_tune_run(run)
+            outs.append(bsm.contract("mnP,nl->mlP", Tl, Ml).values.clone())
+            torch.cuda.synchronize()
+    finally:
+        bsm.bsm_tune_load(None)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])

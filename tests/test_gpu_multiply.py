@@ -211,6 +211,29 @@ def test_work_order_panels_bit_identical(bsm):
     check_against_oracle(bsm, d["A"], d["B"], eps=d["eps"])
 
 
+def test_work_order_runs_bit_identical(bsm):
+    """Runs of consecutive tiles per wavefront change only which wavefront
+    runs a tile: results are bit-identical for every run length, plain and
+    in place with C_in."""
+    d = workloads.banded(nblk=150, seed_tag=32)
+    A = bsm.BlockSparseMatrix.from_workload(d["A"])
+    B = bsm.BlockSparseMatrix.from_workload(d["B"])
+    outs = []
+    try:
+        for run in (1, 2, 7, 32, 4096):
+            bsm.bsm_tune_run(run)
+            assert bsm.bsm_tune_get_run() == run
+            outs.append(bsm.matmul(A, B, filter_eps=d["eps"]).values.clone())
+            torch.cuda.synchronize()
+    finally:
+        bsm.bsm_tune_load(None)
+    assert bsm.bsm_tune_get_run() == 1
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    with pytest.raises(bsm.BsmError):
+        bsm.bsm_tune_run(0)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_plan_stacks_match_oracle(bsm, seed):
     """The symbolic phase alone (no numeric launch): output pattern and every
