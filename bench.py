@@ -114,18 +114,25 @@ def cpu_model():
 
 def cpu_baseline(d, nrows=1000):
     """The CPU oracle (block loop, numpy/BLAS) timed on a bounded sample of
-    output block rows (every second one by default), with BLAS on all of the
-    host's cores and again on one thread."""
-    from threadpoolctl import threadpool_limits
+    output block rows (every second one by default), with BLAS on all the
+    threads its pool uses (the host's cores unless OMP_NUM_THREADS or the like
+    limit them; that count is reported) and again on one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import blocksparse as ob
     A = ob.BlockSparse.from_workload(d["A"])
     B = ob.BlockSparse.from_workload(d["B"])
     n = len(d["A"]["row_sizes"])
     rows = set(range(0, n, max(1, n // nrows)))
-    cores = os.cpu_count() or 1
+
+    def blas_threads():   # what the BLAS pools will actually use
+        t = [p["num_threads"] for p in threadpool_info() if p.get("user_api") == "blas"]
+        return max(t) if t else 1
+
+    cores = blas_threads()
     res = {}
     for threads in (cores, 1):
         with threadpool_limits(threads):
+            assert blas_threads() == threads
             t0 = time.perf_counter()
             _, trip = ob.multiply(A, B, eps=d["eps"], rows=rows)
             res[threads] = time.perf_counter() - t0
@@ -426,7 +433,7 @@ def main():
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_bytes)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

@@ -59,7 +59,7 @@ typedef int32_t bsm_status;
 #define BSM_E_SHAPE -3       /* block sizes of the operands do not conform */
 #define BSM_E_NOMEM -4       /* device or host allocation failed */
 #define BSM_E_DEVICE -5      /* HIP runtime error (launch, copy, async fault) */
-#define BSM_E_UNSUPPORTED -6 /* valid request outside what this build handles */
+#define BSM_E_UNSUPPORTED -6 /* valid request outside what the library handles */
 
 #define BSM_PREC_FP64 0      /* float64 products, float64 accumulation */
 #define BSM_PREC_BF16X3 1    /* split precision: hh + hl + lh bf16 pieces */
@@ -420,7 +420,7 @@ bsm_status bsm_tune_load(const char* path);
 /* Work order of the numeric phase: output tiles of a class are visited in
  * panels of rows x cols output blocks (panels row by row, canonical order
  * inside), so that the wavefronts of an XCD share the A and B blocks of one
- * panel in L2.  rows = cols = 0 keeps the canonical order; default 32 x 32.
+ * panel in L2.  rows = cols = 0 (the default) keeps the canonical order.
  * Applies to plans created afterwards; BSM_E_INVALID for negative sizes or one
  * size 0.  bsm_tune_load also reads an optional "panel": [rows, cols]. */
 bsm_status bsm_tune_panel(int32_t rows, int32_t cols);
@@ -435,6 +435,15 @@ bsm_status bsm_tune_get_panel(int32_t* rows, int32_t* cols);
  * it to 1 without one). */
 bsm_status bsm_tune_run(int32_t run);
 bsm_status bsm_tune_get_run(int32_t* run);
+/* Wavefronts per workgroup of the float64 numeric kernels (1, 2, 4 or 8;
+ * else BSM_E_INVALID).  The wavefronts of one workgroup run on one compute
+ * unit and take consecutive output tiles (or runs) of their XCD's share at
+ * the same time: neighbours in one block row, which read the same A blocks,
+ * so that these meet in the unit's L1.  Read at each execute; results are
+ * bit-identical for every value.  Default 1; bsm_tune_load also reads an
+ * optional "group": G (and resets it to 1 without one). */
+bsm_status bsm_tune_group(int32_t waves);
+bsm_status bsm_tune_get_group(int32_t* waves);
 /* Current table: out16[c] = variant of class c (host array of 16). */
 bsm_status bsm_tune_get(int32_t* out16);
 /* Replace the table (host array of 16 values in {0, 1}; else BSM_E_INVALID).

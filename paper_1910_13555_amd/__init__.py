@@ -27,7 +27,7 @@ __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmu
            "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
            "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
            "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load",
-           "bsm_tune_panel", "bsm_tune_get_panel", "bsm_tune_run", "bsm_tune_get_run", "add", "transpose", "trace", "dot", "filter_blocks",
+           "bsm_tune_panel", "bsm_tune_get_panel", "bsm_tune_run", "bsm_tune_get_run", "bsm_tune_group", "bsm_tune_get_group", "add", "transpose", "trace", "dot", "filter_blocks",
            "identity", "sign_iteration", "slice_tensor", "contract_chunks", "contract_chunked"]
 
 
@@ -429,6 +429,18 @@ def bsm_tune_run(run):
 def bsm_tune_get_run():
     r = np.zeros(1, np.int32)
     check(lib.bsm_tune_get_run(_lib.as_i32p(r)))
+    return int(r[0])
+
+
+def bsm_tune_group(waves):
+    """Wavefronts per workgroup of the numeric kernels (1, 2, 4 or 8): the
+    wavefronts of a workgroup take consecutive output tiles at once."""
+    check(lib.bsm_tune_group(int(waves)))
+
+
+def bsm_tune_get_group():
+    r = np.zeros(1, np.int32)
+    check(lib.bsm_tune_get_group(_lib.as_i32p(r)))
     return int(r[0])
 
 

@@ -105,6 +105,8 @@ PROTOTYPES = {
     "bsm_tune_get_panel": [_i32p, _i32p],
     "bsm_tune_run": [C.c_int32],
     "bsm_tune_get_run": [_i32p],
+    "bsm_tune_group": [C.c_int32],
+    "bsm_tune_get_group": [_i32p],
     "bsm_tune_get": [_i32p],
     "bsm_tune_set": [_i32p],
 }

@@ -21,6 +21,8 @@ const bsm_mm_opts kDefaultOpts = {0, 0, 0, BSM_PREC_FP64};
 int32_t g_panel[2] = {0, 0};
 // Consecutive tiles per wavefront run on the row-major path (bsm_tune_run).
 int32_t g_run = 1;
+// Wavefronts per workgroup of the numeric kernels (bsm_tune_group).
+int32_t g_wpg = 1;
 
 // Work items of the numeric kernel from a tile list: one per (tile, segment
 // of <= 64 products), written on the device; `seg` ends with their count.
@@ -314,6 +316,7 @@ void execute(bsm_plan pl, double alpha, const double* x, const double* y, double
     P.steps = pl->steps.p;
     P.xb = pl->xb.p;
     P.run = g_run;
+    P.wpg = g_wpg;
   }
   std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, P.cls_tile);
   P.ncu = pl->ctx->ncu;
@@ -915,18 +918,38 @@ bsm_status bsm_tune_load(const char* path) {
     }
     g_panel[0] = panel[0];
     g_panel[1] = panel[1];
-    int32_t run = 1;
-    if (path) {
-      const size_t rk = text.find("\"run\"");
-      const size_t rc = rk == std::string::npos ? rk : text.find(':', rk);
-      if (rc != std::string::npos) {
-        char* end = nullptr;
-        const long x = std::strtol(text.c_str() + rc + 1, &end, 10);
-        if (end == text.c_str() + rc + 1 || x < 1 || x > 4096) fail(BSM_E_INVALID, "%s: \"run\" needs 1..4096", path);
-        run = (int32_t)x;
-      }
-    }
+    // scalar fields: the first occurrence of the key (the tuner writes them
+    // before its list of trials)
+    auto int_field = [&](const char* key, long lo, long hi, long dflt) {
+      if (!path) return dflt;
+      const size_t k = text.find(std::string("\"") + key + "\"");
+      const size_t c = k == std::string::npos ? k : text.find(':', k);
+      if (c == std::string::npos) return dflt;
+      char* end = nullptr;
+      const long x = std::strtol(text.c_str() + c + 1, &end, 10);
+      if (end == text.c_str() + c + 1 || x < lo || x > hi) fail(BSM_E_INVALID, "%s: \"%s\" needs %ld..%ld", path, key, lo, hi);
+      return x;
+    };
+    const int32_t run = (int32_t)int_field("run", 1, 4096, 1);
+    const int32_t wpg = (int32_t)int_field("group", 1, kMaxGroupWaves, 1);
+    if (wpg & (wpg - 1)) fail(BSM_E_INVALID, "%s: \"group\" must be a power of two", path);
     g_run = run;
+    g_wpg = wpg;
+  });
+}
+
+bsm_status bsm_tune_group(int32_t waves) {
+  return guard([&] {
+    if (waves < 1 || waves > kMaxGroupWaves || (waves & (waves - 1)))
+      fail(BSM_E_INVALID, "wavefronts per workgroup must be 1, 2, 4 or 8");
+    g_wpg = waves;
+  });
+}
+
+bsm_status bsm_tune_get_group(int32_t* waves) {
+  return guard([&] {
+    if (!waves) fail(BSM_E_INVALID, "NULL output");
+    *waves = g_wpg;
   });
 }
 

@@ -197,6 +197,7 @@ void run_batch(bsm_batch b, const double* alpha, const double* beta, const doubl
   P.ptab = b->ptab.p;
   P.xb = b->xb.p;
   P.run = g_run;
+  P.wpg = g_wpg;
   for (int32_t p = 0; p < n; ++p) P.has_cin |= (t[p].beta != 0.0 && t[p].cin != nullptr) ? 1 : 0;
   P.ncu = ctx->ncu;
   P.mx = b->mx;

@@ -511,6 +511,7 @@ namespace bsm_host {
 // Implemented in bsm_api.cpp.
 extern const bsm_mm_opts kDefaultOpts;
 extern int32_t g_run;   // consecutive tiles per wavefront run (bsm_tune_run)
+extern int32_t g_wpg;   // wavefronts per workgroup of the numeric kernels (bsm_tune_group)
 OpCsr op_csr(bsm_pattern P, bool trans);
 void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, const double* b_vals,
                    const double* b_norms);

@@ -11,6 +11,7 @@
 namespace bsm {
 
 constexpr int kWave = 64;
+constexpr int kMaxGroupWaves = 8;             // wavefronts per workgroup of the numeric kernels, at most
 constexpr int kSymChunk = 2048;               // output columns per bitmap pass
 constexpr int kSymWords = kSymChunk / 32;     // = one 32-bit word per lane of a wavefront
 constexpr int kTile = 32;                     // max output tile edge per work item
@@ -118,6 +119,7 @@ struct NumParams {
   uint32_t xpb = 0, ypb = 0;      // split precision: X / Y are piece arrays of this many bytes each
   const int32_t* xb = nullptr;    // row-major path: XCD share bounds, 9 per class (launch_xcd_bounds)
   int32_t run = 1;                // row-major path: consecutive tiles per wavefront run (work order)
+  int32_t wpg = 1;                // wavefronts per workgroup (1..kMaxGroupWaves, a power of two)
   double* part = nullptr;         // generic path, split-K: kTile * kTile partial sums per work item
   hipEvent_t* ev = nullptr;       // optional: events recorded around kernel family k's launch (2k, 2k+1)
   int32_t* launched = nullptr;    // optional: launched[k] set to 1 when family k ran

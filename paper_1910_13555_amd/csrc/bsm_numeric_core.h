@@ -139,7 +139,7 @@ __host__ __device__ constexpr int kernel_of(int c, int v) {
 }
 
 struct ClassWaves {
-  int32_t w[kClasses + 1];  // class c's wavefronts: [w[c], w[c+1]) of the grid
+  int32_t w[kClasses + 1];  // class c's workgroups: [w[c], w[c+1]) of the grid
 };
 
 // Pipelined loop over this wavefront's tiles of one class; NI x NJ
@@ -149,7 +149,7 @@ struct ClassWaves {
 // continue it.
 template <int V, int NI, int NJ, bool GEN, bool CIN, bool BATCH, int D>
 __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, int r, int stride) {
-  const int l = threadIdx.x;
+  const int l = threadIdx.x & (kWave - 1);
   // lane roles: rows (A) / columns (B) and instruction k index
   const int lrA = V == 0 ? 4 * ((l >> 3) & 1) + (l & 3) : (l & 15);   // row inside an instruction tile
   const int lcB = V == 0 ? 4 * ((l >> 2) & 1) + (l & 3) : (l & 15);   // column inside an instruction tile
@@ -464,7 +464,7 @@ __device__ __forceinline__ void run_tiles(const NumParams& P, int e0, int e1, in
 // take the share's tiles cyclically).
 template <int V, int NI, int NJ, bool CIN, bool BATCH, int D, bool TR>
 __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, int r, int stride) {
-  const int l = threadIdx.x;
+  const int l = threadIdx.x & (kWave - 1);
   const int RL = P.run > 0 ? P.run : 1;
   auto next_tile = [&](int t) __attribute__((always_inline)) {
     const int q = t - e0;
@@ -746,21 +746,28 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   }
 }
 
-// Persistent kernel KID.  Wavefronts [W.w[c], W.w[c+1]) serve class c (a
-// multiple of 8 of them).  Workgroups are dealt to the 8 XCDs round-robin, so
-// local wavefront w runs on XCD w % 8; each XCD owns one contiguous eighth of
-// the class's work items (cut at tile starts), and its wavefronts take that
-// eighth's tiles cyclically.  All wavefronts of an XCD therefore work on
+// Persistent kernel KID.  Workgroups [W.w[c], W.w[c+1]) serve class c (a
+// multiple of 8 of them), P.wpg wavefronts each.  Workgroups are dealt to the
+// 8 XCDs round-robin, so local workgroup g runs on XCD g % 8; each XCD owns
+// one contiguous eighth of the class's work items (cut at tile starts), and
+// its wavefronts take that eighth's tiles cyclically, the wavefronts of one
+// workgroup consecutive tiles.  All wavefronts of an XCD therefore work on
 // neighbouring output blocks at any moment, and the operand blocks those
-// share stay in the XCD's L2.
+// share stay in the XCD's L2; the wavefronts of a workgroup, on one compute
+// unit, work on neighbours in one block row (the same A blocks) at once, so
+// that these also meet in the unit's L1.
 template <bool GEN, bool CIN, bool BATCH, int KID>
 __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* cls_wave) {
   const int b = blockIdx.x;
+  // the wavefront's index in its workgroup, as a scalar (uniform) value, so
+  // that the tile cursor derived from it stays in scalar registers
+  const int wpg = (int)(blockDim.x / kWave);
+  const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   int c = 0;
   while (c < kClasses - 1 && b >= cls_wave[c + 1]) ++c;
-  const int n = cls_wave[c + 1] - cls_wave[c];
-  const int w = b - cls_wave[c];
-  const int x = w % kXcd, r = w / kXcd;
+  const int n = (cls_wave[c + 1] - cls_wave[c]) * wpg;   // wavefronts of the class
+  const int g = b - cls_wave[c];
+  const int x = g % kXcd, r = (g / kXcd) * wpg + v;
   const int64_t d0 = P.seg ? P.seg[P.cls_tile[c]] : P.cls_tile[c];
   const int64_t d1 = P.seg ? P.seg[P.cls_tile[c + 1]] : P.cls_tile[c + 1];
   int e0, e1;
@@ -801,7 +808,8 @@ __device__ __forceinline__ void numeric_body(const NumParams& P, const int32_t* 
 // row-major path, so that the epilogue never waits on memory).  BATCH: the
 // buffers and scalars come from the per-problem table.
 template <bool GEN, bool CIN, bool BATCH, int KID>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kern_waves(KID, GEN, CIN))))
+__global__ void __launch_bounds__(kWave * kMaxGroupWaves)
+__attribute__((amdgpu_waves_per_eu(kern_waves(KID, GEN, CIN))))
 k_numeric(NumParams P, ClassWaves W) {
   numeric_body<GEN, CIN, BATCH, KID>(P, W.w);
 }
@@ -809,10 +817,14 @@ k_numeric(NumParams P, ClassWaves W) {
 namespace {
 
 
-// Wavefronts per class for one kernel: the kernel's resident count split in
-// proportion to tiles x padded tile area, multiples of 8 (one share per XCD),
-// at most one wavefront per tile; classes of other kernels get none.
+// Workgroups (p.wpg wavefronts each) per class for one kernel: the kernel's
+// resident wavefronts split in proportion to tiles x padded tile area,
+// multiples of 8 workgroups (one share per XCD), at most one wavefront per
+// tile (rounded up to whole workgroups per XCD); classes of other kernels get
+// none.
 ClassWaves class_waves(const NumParams& p, int kid, int resident) {
+  const int wpg = std::max(1, p.wpg);
+  resident = std::max(kXcd, resident / wpg);
   ClassWaves cw;
   double wsum = 0.0;
   for (int c = 0; c < kClasses; ++c)
@@ -824,7 +836,7 @@ ClassWaves class_waves(const NumParams& p, int kid, int resident) {
     if (nt > 0 && kernel_of(c, g_variant[c]) == kid) {
       const double share = double(nt) * ((c / 4 + 1) * (c % 4 + 1)) / wsum;
       w = std::max<int64_t>(kXcd, ((int64_t)(share * resident) / kXcd) * kXcd);
-      w = std::min<int64_t>(w, ((nt + kXcd - 1) / kXcd) * kXcd);
+      w = std::min<int64_t>(w, ((nt + kXcd * wpg - 1) / (kXcd * wpg)) * kXcd);
     }
     cw.w[c + 1] = (int32_t)(cw.w[c] + w);
   }
@@ -846,6 +858,7 @@ hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
     nfam += cw[kid].w[kClasses] > 0;
   }
   const bool conc = p.side && nfam > 1;
+  const unsigned block = (unsigned)(kWave * std::max(1, p.wpg));
   hipError_t e;
   if (conc && (e = hipEventRecord(p.fork, s)) != hipSuccess) return e;
   int nside = 0;
@@ -861,11 +874,11 @@ hipError_t launch_kernels(hipStream_t s, const NumParams& p) {
     first = false;
     if (p.ev && (e = hipEventRecord(p.ev[2 * kid], ls)) != hipSuccess) return e;
     switch (kid) {
-      case 0: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 0>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
-      case 1: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 1>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
-      case 2: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 2>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
-      case 3: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 3>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
-      default: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 4>), dim3(W), dim3(64), 0, ls, p, cw[kid]); break;
+      case 0: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 0>), dim3(W), dim3(block), 0, ls, p, cw[kid]); break;
+      case 1: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 1>), dim3(W), dim3(block), 0, ls, p, cw[kid]); break;
+      case 2: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 2>), dim3(W), dim3(block), 0, ls, p, cw[kid]); break;
+      case 3: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 3>), dim3(W), dim3(block), 0, ls, p, cw[kid]); break;
+      default: hipLaunchKernelGGL((k_numeric<GEN, CIN, BATCH, 4>), dim3(W), dim3(block), 0, ls, p, cw[kid]); break;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (p.ev) {

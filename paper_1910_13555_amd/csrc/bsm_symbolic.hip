@@ -100,10 +100,14 @@ __global__ void __launch_bounds__(256) k_block_norms(int64_t nblk, const int64_t
   if (l == 0) out[b] = s;
 }
 
-// Both operands' norms in one launch, four blocks per wavefront with their
-// loads interleaved (more memory requests in flight per wavefront); each
-// block's arithmetic is exactly that of k_block_norms.
+// Both operands' norms in one launch, four blocks per wavefront; each lane
+// issues its loads of all four blocks for up to kNormUnroll elements each
+// before it adds any of them, so a wavefront waits for memory once per 512
+// elements of its blocks (usually once) instead of once per 64.  Each
+// block's arithmetic is exactly that of k_block_norms: lane l adds the
+// squares of elements l, l + 64, ... in that order.
 constexpr int kNormBlocks = 4;
+constexpr int kNormUnroll = 8;
 __global__ void __launch_bounds__(256) k_block_norms2(int64_t na, const int64_t* __restrict__ offa,
                                                       const double* __restrict__ va, double* __restrict__ outa,
                                                       int64_t nb, const int64_t* __restrict__ offb,
@@ -131,16 +135,23 @@ __global__ void __launch_bounds__(256) k_block_norms2(int64_t na, const int64_t*
   double s[kNormBlocks];
 #pragma unroll
   for (int q = 0; q < kNormBlocks; ++q) s[q] = 0.0;
-  for (int64_t e = l; e < lmax; e += kWave) {
-    double x[kNormBlocks];
-#pragma unroll
-    for (int q = 0; q < kNormBlocks; ++q) x[q] = e < len[q] ? v[base[q] + e] : 0.0;
+  for (int64_t e0 = l; e0 < lmax; e0 += kWave * kNormUnroll) {
+    double x[kNormBlocks][kNormUnroll];
 #pragma unroll
     for (int q = 0; q < kNormBlocks; ++q)
-      if (e < len[q]) {
-        const double sq = x[q] * x[q];
-        s[q] = s[q] + sq;
+#pragma unroll
+      for (int u = 0; u < kNormUnroll; ++u) {
+        const int64_t e = e0 + u * kWave;
+        x[q][u] = e < len[q] ? v[base[q] + e] : 0.0;
       }
+#pragma unroll
+    for (int q = 0; q < kNormBlocks; ++q)
+#pragma unroll
+      for (int u = 0; u < kNormUnroll; ++u)
+        if (e0 + u * kWave < len[q]) {
+          const double sq = x[q][u] * x[q][u];
+          s[q] = s[q] + sq;
+        }
   }
 #pragma unroll
   for (int q = 0; q < kNormBlocks; ++q) {

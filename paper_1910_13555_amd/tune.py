@@ -1,7 +1,7 @@
 """Autotuner of the numeric phase: picks, per output tile class, the
 matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4), then the run length
-of the work order (consecutive tiles per wavefront), then the output panel
-of the work order, that run a workload fastest, by timing the numeric phase
+of the work order (consecutive tiles per wavefront), then the wavefronts
+per workgroup, then the output panel of the work order, that run a workload fastest, by timing the numeric phase
 on the GPU (coordinate descent over the 16 classes starting from the
 built-in table, then scans of run lengths and panel edges), and writes the
 result as JSON for bsm_tune_load.
@@ -101,6 +101,15 @@ def tune(workload="banded", reps=10, min_gain=0.02):
         if t < best * (1.0 - min_gain):
             run, best = r, t
     bsm.bsm_tune_run(run)
+    # wavefronts per workgroup: also read at execute time
+    group = 1
+    for g in (2, 4, 8):
+        bsm.bsm_tune_group(g)
+        t = _time(fn, reps)
+        trials.append({"group": g, "ms": t})
+        if t < best * (1.0 - min_gain):
+            group, best = g, t
+    bsm.bsm_tune_group(group)
     del keep, fn
     # work order: output panel edge (plans are rebuilt, the order is fixed at plan time;
     # not scanned for the rank-3 contraction, whose inputs take minutes to regenerate)
@@ -114,7 +123,7 @@ def tune(workload="banded", reps=10, min_gain=0.02):
         if t < best * (1.0 - min_gain):
             panel, best = (edge, edge), t
     bsm.bsm_tune_panel(*panel)
-    return {"workload": workload, "variant": table, "run": run, "panel": list(panel), "default_ms": start,
+    return {"workload": workload, "variant": table, "run": run, "group": group, "panel": list(panel), "default_ms": start,
             "tuned_ms": best, "trials": trials}
 
 
@@ -130,7 +139,7 @@ def main():
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
-    print(json.dumps({k: res[k] for k in ("workload", "variant", "run", "panel", "default_ms", "tuned_ms")}), flush=True)
+    print(json.dumps({k: res[k] for k in ("workload", "variant", "run", "group", "panel", "default_ms", "tuned_ms")}), flush=True)
 
 
 if __name__ == "__main__":

@@ -234,6 +234,54 @@ def test_work_order_runs_bit_identical(bsm):
         bsm.bsm_tune_run(0)
 
 
+def test_workgroup_sizes_bit_identical(bsm):
+    """Wavefronts per workgroup (1, 2, 4, 8), alone and with runs of tiles,
+    change only where a tile runs: bit-identical results on the row-major
+    path with and without C_in (beta = 0.5), on the generic-layout path
+    (transposed operands) and for a batch; the result with one wavefront
+    per workgroup is checked against the oracle."""
+    d = workloads.banded(nblk=150, seed_tag=33)
+    A = bsm.BlockSparseMatrix.from_workload(d["A"])
+    B = bsm.BlockSparseMatrix.from_workload(d["B"])
+    ctx = A.pattern.ctx
+    Cm = bsm.matmul(A, B, filter_eps=d["eps"])
+    At = bsm.transpose(A)
+    plan = bsm.bsm_multiply_plan(ctx, A.pattern, A.values, B.pattern, B.values, Cm.pattern, d["eps"])
+    tplan = bsm.bsm_multiply_plan(ctx, At.pattern, At.values, B.pattern, B.values, None, d["eps"], trans_a=True)
+    rng = np.random.default_rng(34)
+    sz = np.array([5, 13, 23] * 6, np.int32)
+    small = [workloads.random_matrix(rng, sz, sz, 0.3) for _ in range(4)]
+    mats = [bsm.BlockSparseMatrix.from_workload(x) for x in small]
+    bplans = [bsm.bsm_multiply_plan(ctx, mats[i].pattern, mats[i].values, mats[i + 1].pattern, mats[i + 1].values,
+                                    None, 0.0) for i in range(3)]
+    batch = bsm.bsm_batch_create(ctx, bplans)
+    results = []
+    try:
+        for group, run in ((1, 1), (2, 1), (4, 1), (8, 1), (4, 3), (8, 16)):
+            bsm.bsm_tune_group(group)
+            bsm.bsm_tune_run(run)
+            assert bsm.bsm_tune_get_group() == group
+            o1 = plan.execute(1.0, A.values, B.values, 0.0, None)
+            o2 = plan.execute(0.75, A.values, B.values, 0.5, Cm.values)
+            o3 = tplan.execute(1.0, At.values, B.values, 0.0, None)
+            o4 = batch.execute(1.0, [m.values for m in mats[:3]], [m.values for m in mats[1:]])
+            torch.cuda.synchronize()
+            results.append([o1.clone(), o2.clone(), o3.clone()] + [o.clone() for o in o4])
+    finally:
+        bsm.bsm_tune_load(None)
+    assert bsm.bsm_tune_get_group() == 1
+    for r in results[1:]:
+        for a, b in zip(r, results[0]):
+            assert torch.equal(a, b)
+    oA, oB = ob.BlockSparse.from_workload(d["A"]), ob.BlockSparse.from_workload(d["B"])
+    ref, _ = ob.multiply(oA, oB, eps=d["eps"])
+    got = to_oracle(Cm.pattern, results[0][0], ref.row_sizes, ref.col_sizes)
+    assert_close(got, ref, TOL, ob.multiply_error_bound(oA, oB, eps=d["eps"]))
+    for bad in (0, 3, 16):
+        with pytest.raises(bsm.BsmError):
+            bsm.bsm_tune_group(bad)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_plan_stacks_match_oracle(bsm, seed):
     """The symbolic phase alone (no numeric launch): output pattern and every
