@@ -467,6 +467,7 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
   const int l = threadIdx.x & (kWave - 1);
   const int RL = P.run > 0 ? P.run : 1;
   auto next_tile = [&](int t) __attribute__((always_inline)) {
+    if (RL == 1) return t + stride;   // (no division on the default order)
     const int q = t - e0;
     return (q + 1) % RL ? t + 1 : t + 1 + (stride - 1) * RL;
   };

@@ -1,10 +1,11 @@
 """Autotuner of the numeric phase: picks, per output tile class, the
 matrix-core variant (0 = FP64 4x4x4, 1 = FP64 16x16x4), then the run length
-of the work order (consecutive tiles per wavefront), then the wavefronts
-per workgroup, then the output panel of the work order, that run a workload fastest, by timing the numeric phase
-on the GPU (coordinate descent over the 16 classes starting from the
-built-in table, then scans of run lengths and panel edges), and writes the
-result as JSON for bsm_tune_load.
+of the work order (consecutive tiles per wavefront), then the wavefronts per
+workgroup, then the output panel of the work order, that run a workload
+fastest, by timing the numeric phase on the GPU (coordinate descent over
+the 16 classes starting from the built-in table, then scans of run lengths,
+workgroup sizes and panel edges), and writes the result as JSON for
+bsm_tune_load.
 
 Usage: python -m paper_1910_13555_amd.tune [--workload banded|batched|tall_skinny|rank3]
                                            [--out FILE] [--reps N]
