@@ -368,21 +368,24 @@ def rank3_section(bsm, reps, stream):
            "forward_compulsory_gb": comp / 1e9,
            "forward_hbm_frac": comp / (fwd_ms * 1e-3) / PEAK_HBM,
            "forward_backward_ms": fb_ms, "forward_backward_gflops": 3 * F / (fb_ms * 1e-3) / 1e9}
+    r_values = out.values.numel()
     del out, g
     T.values.grad = None
     M.values.grad = None
+    ctx.release_cache()          # the one-piece runs' buffers
     torch.cuda.empty_cache()
-    res["chunked"] = rank3_chunked(bsm, T, M, F)
+    res["chunked"] = rank3_chunked(bsm, T, M, F, r_values)
     return res
 
 
-def rank3_chunked(bsm, T, M, F, budget=16 << 30):
+def rank3_chunked(bsm, T, M, F, r_values, budget=16 << 30):
     """The same contraction and its gradient streamed in chunks of the tall
     first mode under a device-memory budget for each chunk (two chunks in
     flight on two streams): each chunk's output is reduced (<1, R_c>) and
     its gradient (ones) handed back, so R is never held whole.  The device
     memory in use beyond the inputs and their gradients is sampled (free
-    memory) at every chunk; the second of two runs is timed."""
+    memory) at every chunk of a first run that starts from empty caches; the
+    second run is timed."""
     import torch
     Tv, Mv = T.values.detach(), M.values.detach()
     Tt = bsm.BlockSparseTensor(T.pattern, Tv)
@@ -395,18 +398,25 @@ def rank3_chunked(bsm, T, M, F, budget=16 << 30):
         Rc.values.sum()
         return torch.ones_like(Rc.values)
 
-    for _ in range(2):
-        torch.cuda.synchronize()
-        torch.cuda.empty_cache()
-        free0 = torch.cuda.mem_get_info()[0]
-        used.clear()
-        t0 = time.perf_counter()
-        bounds = bsm.contract_chunked("mnP,nl->mlP", Tt, Mt, budget, consume, dT1=dT, dT2=dM)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+    # run 1 from empty caches: the growth of device memory in use is the
+    # chunked run's working set (torch's and the library's caches grow to
+    # it and keep it); run 2 reuses those caches and is timed
+    torch.cuda.synchronize()
+    bsm.release_chunk_contexts()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    bounds = bsm.contract_chunked("mnP,nl->mlP", Tt, Mt, budget, consume, dT1=dT, dT2=dM)
+    torch.cuda.synchronize()
+    peak = max(used + [free0 - torch.cuda.mem_get_info()[0]])
+    t0 = time.perf_counter()
+    bounds = bsm.contract_chunked("mnP,nl->mlP", Tt, Mt, budget, consume, dT1=dT, dT2=dM)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    bsm.release_chunk_contexts()
     return {"chunks": len(bounds) - 1, "budget_gb": budget / 2 ** 30, "forward_backward_ms": ms,
             "forward_backward_gflops": 3 * F / (ms * 1e-3) / 1e9,
-            "max_gb_in_use_beyond_inputs_and_gradients": max(used) / 2 ** 30}
+            "working_set_gb": peak / 2 ** 30,
+            "unchunked_output_and_gradient_gb": 16.0 * r_values / 2 ** 30}
 
 
 def main():
@@ -495,13 +505,19 @@ def main():
     ms_step = sum(per_step) / args.steps
     numeric_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / args.steps
     info = plan.info
-    # per-phase device times of one more step (library events on its stream)
+    # per-phase device times (library events on its stream): median of five
+    # more steps, each after the cache eviction
     ctx.set_timing(True)
-    evict.fill_(1)
-    plan2, out2 = step()
-    phases = [round(x, 4) for x in ctx.phase_times()]
+    ph = []
+    for k in range(5):
+        evict.fill_(k + 1)
+        torch.cuda.synchronize()
+        plan2, out2 = step()
+        ph.append(ctx.phase_times())
+        del plan2, out2
+    phases = [round(sorted(p[i] for p in ph)[2], 4) for i in range(4)]
     ctx.set_timing(False)
-    del plan2, out2, evict
+    del evict
 
     # numeric phase alone (plan reuse, as in repeated multiplies with a fixed pattern)
     reuse_ms = time_events(lambda: plan.execute(1.0, A.values, B.values, 0.0, None, out), args.steps,

@@ -105,6 +105,13 @@ bsm_status bsm_ctx_set_stream(bsm_ctx ctx, void* stream);
 /* Wait for the context's stream; reports asynchronous device errors. */
 bsm_status bsm_sync(bsm_ctx ctx);
 bsm_status bsm_ctx_destroy(bsm_ctx ctx);
+/* Return the device memory the context's own caching allocator holds for
+ * reuse (blocks of destroyed plans, patterns and temporaries) to the device,
+ * after waiting for the context's stream; *released (may be NULL) receives
+ * the bytes.  Memory of live objects is untouched; nothing is cached for a
+ * context with caller allocator callbacks (0 bytes).  BSM_E_INVALID for a
+ * NULL context, BSM_E_DEVICE if the wait fails. */
+bsm_status bsm_ctx_release_cache(bsm_ctx ctx, size_t* released);
 /* Launch timing of the FP64 numeric kernels, for measurement: with on != 0,
  * each bsm_plan_execute on this context records HIP events on the context's
  * stream around each of its numeric kernel launches (five kernel families:

@@ -27,7 +27,7 @@ __all__ = ["Context", "Pattern", "Plan", "BlockSparseMatrix", "BsmError", "matmu
            "bsm_ctx_create", "bsm_pattern_create", "bsm_block_norms", "bsm_multiply_plan",
            "bsm_plan_execute", "bsm_plan_backward", "bsm_multiply", "default_context", "Batch",
            "bsm_batch_create", "bsm_batch_execute", "bsm_tune_get", "bsm_tune_set", "bsm_tune_load",
-           "bsm_tune_panel", "bsm_tune_get_panel", "bsm_tune_run", "bsm_tune_get_run", "bsm_tune_group", "bsm_tune_get_group", "add", "transpose", "trace", "dot", "filter_blocks",
+           "bsm_tune_panel", "bsm_tune_get_panel", "bsm_tune_run", "bsm_tune_get_run", "release_chunk_contexts", "bsm_tune_group", "bsm_tune_get_group", "add", "transpose", "trace", "dot", "filter_blocks",
            "identity", "sign_iteration", "slice_tensor", "contract_chunks", "contract_chunked"]
 
 
@@ -113,6 +113,13 @@ class Context:
 
     def sync(self):
         check(lib.bsm_sync(self.handle))
+
+    def release_cache(self):
+        """Return the memory the library caches for this context to the
+        device (bsm_ctx_release_cache); returns the bytes released."""
+        n = C.c_size_t(0)
+        check(lib.bsm_ctx_release_cache(self.handle, C.byref(n)))
+        return int(n.value)
 
     def set_timing(self, on: bool):
         """Record HIP events around each numeric kernel launch of later executes."""
@@ -789,11 +796,13 @@ def contract_chunked(spec: str, T1, T2, max_bytes: int, consume, alpha=1.0, filt
     gradient of T2 is added into dT2 in chunk order (deterministic).  dT1 /
     dT2: float64 tensors in T1's / T2's layout, or None.  allocator: that of
     the chunks' contexts (see Context; "torch" makes torch's memory
-    statistics cover the library's buffers too).  Returns the chunk bounds."""
+    statistics cover the library's buffers too).  With the library's own
+    allocator the streams and contexts are kept for later calls with the same
+    device and stream count, and so is the memory they cache
+    (release_chunk_contexts returns it).  Returns the chunk bounds."""
     bounds = contract_chunks(spec, T1, T2, max_bytes)
     dev = T1.values.device
-    streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
-    ctxs = [Context(dev.index or 0, s.cuda_stream, allocator) for s in streams]
+    streams, ctxs = _chunk_streams(dev, nstreams, allocator)
     done = [None] * nstreams         # event: the previous chunk on that stream is finished
     acc_ev = None                    # event: dT2 holds the sum of the chunks so far
     lhs, o = spec.replace(" ", "").split("->")
@@ -835,6 +844,29 @@ def contract_chunked(spec: str, T1, T2, max_bytes: int, consume, alpha=1.0, filt
         if ev is not None:
             cur.wait_event(ev)
     return bounds
+
+
+# Streams and contexts of contract_chunked, kept per device and stream count
+# for later calls (with the library's own allocator), so that the chunks of
+# a later call reuse the device memory the earlier ones cached.
+_CHUNK_POOL = {}
+
+
+def _chunk_streams(dev, nstreams, allocator):
+    key = (dev.index or 0, nstreams)
+    if allocator is None and key in _CHUNK_POOL:
+        return _CHUNK_POOL[key]
+    streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
+    ctxs = [Context(dev.index or 0, s.cuda_stream, allocator) for s in streams]
+    if allocator is None:
+        _CHUNK_POOL[key] = (streams, ctxs)
+    return streams, ctxs
+
+
+def release_chunk_contexts():
+    """Return the memory cached by contract_chunked's kept contexts to the
+    device (their streams are waited for); returns the bytes released."""
+    return sum(ctx.release_cache() for _, ctxs in _CHUNK_POOL.values() for ctx in ctxs)
 
 
 def _clone_tpattern(ctx, P):

@@ -54,6 +54,7 @@ PROTOTYPES = {
     "bsm_ctx_set_stream": [_vp, _vp],
     "bsm_sync": [_vp],
     "bsm_ctx_destroy": [_vp],
+    "bsm_ctx_release_cache": [_vp, C.POINTER(C.c_size_t)],
     "bsm_pattern_create": [_vp, C.c_int32, _i32p, C.c_int32, _i32p, C.c_int64, _i32p, _i32p,
                            _i64p, C.POINTER(_vp)],
     "bsm_pattern_info": [_vp, _i32p, _i32p, _i64p, _i64p],

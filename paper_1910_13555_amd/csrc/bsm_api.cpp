@@ -642,6 +642,18 @@ bsm_status bsm_ctx_phase_times(bsm_ctx ctx, float* ms_out) {
   });
 }
 
+bsm_status bsm_ctx_release_cache(bsm_ctx ctx, size_t* released) {
+  return guard([&] {
+    if (!ctx) fail(BSM_E_INVALID, "NULL context");
+    if (released) *released = ctx->mem.cached_bytes;
+    if (ctx->mem.cached_bytes == 0) return;
+    // cached blocks may still be read by work queued on the context's stream
+    set_device(ctx);
+    hip_check(hipStreamSynchronize(ctx->stream), "stream sync");
+    ctx->mem.release_cache();
+  });
+}
+
 bsm_status bsm_ctx_destroy(bsm_ctx ctx) {
   return guard([&] {
     ctx_release(ctx);

@@ -126,3 +126,24 @@ def test_phase_times(bsm):
     ctx.set_timing(False)
     with pytest.raises(bsm.BsmError):
         ctx.phase_times()
+
+
+def test_release_cache(bsm):
+    """bsm_ctx_release_cache: the blocks of a destroyed plan come back as
+    cached bytes, are returned once (then 0), the context keeps working and
+    gives the same result; a context with caller callbacks caches nothing."""
+    ctx = bsm.Context(0)
+    d, A, B = problem(bsm, ctx)
+    plan, out = multiply(bsm, ctx, A, B, d, "fp64")
+    first = out.clone()
+    del plan
+    assert ctx.release_cache() > 0
+    assert ctx.release_cache() == 0
+    plan, out = multiply(bsm, ctx, A, B, d, "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(out, first)
+    cctx = bsm.Context(0, allocator="torch")
+    d2, A2, B2 = problem(bsm, cctx)
+    p2, _ = multiply(bsm, cctx, A2, B2, d2, "fp64")
+    del p2
+    assert cctx.release_cache() == 0

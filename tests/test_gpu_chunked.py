@@ -102,3 +102,29 @@ def test_chunked_forward_and_backward(bsm, nstreams):
     assert_tensor_close(tensor_to_oracle(M.pattern, cdM, rM.mode_sizes), g2, 1e-12, b2)
     assert_tensor_close(tensor_to_oracle(Rt.pattern, R, ref.mode_sizes), ref, 1e-12,
                         ot.contract_error_bound(rT, rM, SPEC, alpha=0.75))
+
+
+def test_chunk_contexts_kept_between_calls(bsm):
+    """contract_chunked keeps its streams and contexts for the next call:
+    a second call gives bit-identical chunk outputs and gradients, and
+    release_chunk_contexts returns the memory they cached."""
+    d, T, M = case(bsm, tag=103)
+    budget = 8 * (2 * T.values.numel()) // 3
+    runs = []
+    for _ in range(2):
+        outs = {}
+
+        def consume(c, Rc, stream):
+            outs[c] = Rc.values.clone()
+            return torch.ones_like(Rc.values)
+
+        dT, dM = torch.empty_like(T.values), torch.empty_like(M.values)
+        bsm.contract_chunked(SPEC, T, M, budget, consume, dT1=dT, dT2=dM)
+        torch.cuda.synchronize()
+        runs.append((outs, dT, dM))
+    (o1, t1, m1), (o2, t2, m2) = runs
+    assert sorted(o1) == sorted(o2) and len(o1) >= 2
+    for c in o1:
+        assert torch.equal(o1[c], o2[c])
+    assert torch.equal(t1, t2) and torch.equal(m1, m2)
+    assert bsm.release_chunk_contexts() > 0
