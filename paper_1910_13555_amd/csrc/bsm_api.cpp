@@ -190,12 +190,9 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     // tile at most)
     pl->nsteps = h[kFSteps] + (split ? 2 : 1) * pl->ntasks;
     if (pl->nsteps >= (int64_t(1) << 31) - 1) fail(BSM_E_UNSUPPORTED, "more than 2^31-2 product steps");
-    DBuf<int64_t> ch(ctx, pl->nprod + 1), chs(ctx, pl->nprod + 2), ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1);
+    DBuf<int64_t> ns(ctx, pl->ntasks), sb(ctx, pl->ntasks + 1);
     DBuf<int32_t> b2t(ctx, pl->c_nblk);
-    hip_check(launch_product_chunks(st, pl->nprod, pl->px.p, split, ch.p), "product chunks");
-    DBuf<int64_t> scr1(ctx, scan_scratch_size(1, std::max<int64_t>(pl->nprod, 1)));
-    hip_check(launch_scan(st, 1, pl->nprod, ch.p, chs.p, nullptr, scr1.p), "chunk scan");
-    hip_check(launch_tile_steps(st, (int32_t)pl->ntasks, pl->c_nblk, pl->tasks.p, pl->pptr.p, chs.p, pl->c_row.p,
+    hip_check(launch_tile_steps(st, (int32_t)pl->ntasks, pl->c_nblk, pl->tasks.p, pl->pptr.p, pl->px.p, pl->c_row.p,
                                 pl->c_col.p, pl->c_rs, pl->c_cs, split, ns.p, b2t.p),
               "tile steps");
     DBuf<int64_t> scr2(ctx, scan_scratch_size(1, pl->ntasks));
@@ -203,14 +200,14 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     pl->steps = DBuf<uint64_t>(ctx, 2 * pl->nsteps);
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
     hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
-                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, chs.p,
+                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs,
                                 pl->rowq.p, pm, pl->steps.p, pl->sdesc.p),
               "work items");
     ClassBounds cb;
     std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, cb.cls);
     pl->xb = DBuf<int32_t>(ctx, 9 * kClasses);
     hip_check(launch_xcd_bounds(st, pl->sdesc.p, nullptr, cb, pl->xb.p), "XCD shares");
-    hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, chs.p, b2t.p, sb.p, pl->c_col.p,
+    hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, b2t.p, sb.p, pl->c_col.p,
                                    pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
               "product steps");
   }

@@ -178,10 +178,10 @@ hipError_t launch_panel_order(hipStream_t s, int32_t ntiles, int2* tiles, const 
                               int32_t pc, void* scratch, int64_t scratch_bytes);
 // bsm_steps.hip: step lists of the row-major path (one work item per tile,
 // 16-byte step records; see the file's header).
-// Product-parallel step building: chunks per product; per-tile step counts
-// (and the single-tile block map); work items, empty-tile steps and steps of
-// multi-tile blocks; steps of single-tile blocks per product.
-hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, bool split, int64_t* chunks);
+// Step building: per-tile step counts from the tiles' product lists (and
+// the single-tile block map); with their prefix, work items, empty steps and
+// steps of multi-tile blocks, one thread per tile; steps of single-tile
+// blocks, one thread per product.
 // Split precision: the padded piece layout of both operands -- element
 // offsets of their stored blocks (ascending, n + 1 entries) and the offsets
 // of the same blocks in the piece arrays.  Null apad: a float64 plan.
@@ -194,18 +194,18 @@ struct PieceMap {
   int64_t nb = 0;
 };
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
-                             const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
+                             const int64_t* px, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
                              const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile);
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, const int64_t* chs,
+                             const int32_t* rs, const int32_t* cs,
                              const int32_t* rowq /* output split factor per block row, or null */,
                              const PieceMap& pm, uint64_t* steps, TaskDesc* desc);
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
-                                const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
-                                const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
-                                const PieceMap& pm, uint64_t* steps);
+                                const int32_t* blk2tile, const int64_t* sbase, const int32_t* c_col,
+                                const int32_t* cs, const int64_t* px, const int64_t* py, const PieceMap& pm,
+                                uint64_t* steps);
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);

@@ -59,40 +59,35 @@ __device__ __forceinline__ void step_words(int64_t xb, int64_t yb, int K, int N,
   }
 }
 
-// Product-parallel form.  chunks[p] = ceil(K_p / L) for every product.
-__global__ void k_product_chunks(int64_t nprod, const int64_t* __restrict__ px, int L, int64_t* __restrict__ chunks) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprod) return;
-  const int K = (int)((uint64_t)px[p] >> 48);
-  chunks[p] = (K + L - 1) / L;
-}
-
-// Per tile: step count from the product chunk prefix (chs, exclusive, nprod + 1
-// entries); blk2tile[t] = w for blocks that are a single tile, -1 otherwise.
+// Per tile: its step count, the sum over its block's products of
+// ceil(K / L) (one step for a tile without products; split plans: padded to
+// even length, two steps without products); blk2tile[t] = w for blocks that
+// are a single tile, -1 otherwise.
 __global__ void k_tile_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ pptr,
-                             const int64_t* __restrict__ chs, const int32_t* __restrict__ c_row,
+                             const int64_t* __restrict__ px, int L, const int32_t* __restrict__ c_row,
                              const int32_t* __restrict__ c_col, const int32_t* __restrict__ rs,
                              const int32_t* __restrict__ cs, int split, int64_t* __restrict__ nsteps,
                              int32_t* __restrict__ blk2tile) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
   const int t = tiles[w].x;
-  const int64_t n = chs[pptr[t + 1]] - chs[pptr[t]];
+  int64_t n = 0;
+  for (int64_t p = pptr[t], p1 = pptr[t + 1]; p < p1; ++p) n += ((int)((uint64_t)px[p] >> 48) + L - 1) / L;
   nsteps[w] = split ? (n > 0 ? (n + 1) & ~int64_t(1) : 2) : (n > 0 ? n : 1);
   const bool single = rs[c_row[t]] <= kTile && cs[c_col[t]] <= kTile;
   if (single) blk2tile[t] = w;
 }
 
-// Per tile: the work item; the one step of a tile without products; the
-// steps of tiles of multi-tile blocks (serially, those are rare).
+// Per tile: the work item; the steps of tiles of multi-tile blocks
+// (serially, those are rare); the empty steps (the one of a tile without
+// products, or a split plan's padding).
 __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ sbase,
                              const int32_t* __restrict__ c_row, const int32_t* __restrict__ c_col,
                              const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
                              const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
                              const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, const int64_t* __restrict__ chs,
-                             const int32_t* __restrict__ rowq, PieceMap pm, uint64_t* __restrict__ steps,
-                             TaskDesc* __restrict__ desc) {
+                             const int32_t* __restrict__ cs, const int32_t* __restrict__ rowq, PieceMap pm,
+                             uint64_t* __restrict__ steps, TaskDesc* __restrict__ desc) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= ntiles) return;
   const int t = tiles[w].x;
@@ -117,44 +112,48 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
   d.cls = (uint16_t)tile_class(mt, nt);
   d.pid = 0;
   desc[w] = d;
-  // empty steps: the tile's only one(s) without products, else the padding
-  // after its real steps
-  for (int64_t q = p0 == p1 ? s : s + (chs[p1] - chs[p0]); q < s + d.np; ++q) {
-    steps[2 * q] = 0;
-    steps[2 * q + 1] = 0;
-  }
-  if (p0 == p1) return;
-  if (M <= kTile && N <= kTile) return;  // written per product
+  const int L = step_k_len(pm.apad != nullptr);
+  const bool single = M <= kTile && N <= kTile;   // steps written per product
   for (int64_t p = p0; p < p1; ++p) {
     const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
+    const int K = (int)(xw >> 48);
+    if (single) {
+      s += (K + L - 1) / L;
+      continue;
+    }
     int64_t xb, yb;
     product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
-    const int K = (int)(xw >> 48);
-    for (int k0 = 0; k0 < K; k0 += step_k_len(pm.apad != nullptr), ++s)
-      step_words(xb, yb, K, N, r0, c0, k0, pm.apad != nullptr, steps + 2 * s);
+    for (int k0 = 0; k0 < K; k0 += L, ++s) step_words(xb, yb, K, N, r0, c0, k0, pm.apad != nullptr, steps + 2 * s);
+  }
+  // empty steps: the tile's only one(s) without products, else the padding
+  // after its real steps
+  for (const int64_t e = d.pbeg + d.np; s < e; ++s) {
+    steps[2 * s] = 0;
+    steps[2 * s + 1] = 0;
   }
 }
 
 // Per product of a single-tile block: its steps at the tile's base plus the
-// chunks of the block's earlier products.
+// steps of the block's earlier products.
 __global__ void k_product_steps(int64_t nprod, const int32_t* __restrict__ pblk, const int64_t* __restrict__ pptr,
-                                const int64_t* __restrict__ chs, const int32_t* __restrict__ blk2tile,
-                                const int64_t* __restrict__ sbase, const int32_t* __restrict__ c_col,
-                                const int32_t* __restrict__ cs, const int64_t* __restrict__ px,
-                                const int64_t* __restrict__ py, PieceMap pm, uint64_t* __restrict__ steps) {
+                                const int32_t* __restrict__ blk2tile, const int64_t* __restrict__ sbase,
+                                const int32_t* __restrict__ c_col, const int32_t* __restrict__ cs,
+                                const int64_t* __restrict__ px, const int64_t* __restrict__ py, PieceMap pm,
+                                uint64_t* __restrict__ steps) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprod) return;
   const int64_t t = pblk[p];          // the block of product p
   const int w = blk2tile[t];
   if (w < 0) return;
   const int N = cs[c_col[t]];
-  int64_t s = sbase[w] + (chs[p] - chs[pptr[t]]);
+  const int L = step_k_len(pm.apad != nullptr);
+  int64_t s = sbase[w];
+  for (int64_t q = pptr[t]; q < p; ++q) s += ((int)((uint64_t)px[q] >> 48) + L - 1) / L;
   const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
   int64_t xb, yb;
   product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
   const int K = (int)(xw >> 48);
-  for (int k0 = 0; k0 < K; k0 += step_k_len(pm.apad != nullptr), ++s)
-    step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
+  for (int k0 = 0; k0 < K; k0 += L, ++s) step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -164,15 +163,8 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 }  // namespace
 
-hipError_t launch_product_chunks(hipStream_t s, int64_t nprod, const int64_t* px, bool split, int64_t* chunks) {
-  if (nprod == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_product_chunks, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, px,
-                     step_k_len(split), chunks);
-  return hipGetLastError();
-}
-
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
-                             const int64_t* chs, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
+                             const int64_t* px, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
                              const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile) {
   if (nblk > 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, blk2tile, nblk, -1);
@@ -180,29 +172,29 @@ hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const 
     if (e != hipSuccess) return e;
   }
   if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, pptr, chs, c_row,
-                     c_col, rs, cs, (int)split, nsteps, blk2tile);
+  hipLaunchKernelGGL(k_tile_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, pptr, px,
+                     step_k_len(split), c_row, c_col, rs, cs, (int)split, nsteps, blk2tile);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
-                             const int32_t* rs, const int32_t* cs, const int64_t* chs, const int32_t* rowq,
-                             const PieceMap& pm, uint64_t* steps, TaskDesc* desc) {
+                             const int32_t* rs, const int32_t* cs, const int32_t* rowq, const PieceMap& pm,
+                             uint64_t* steps, TaskDesc* desc) {
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, chs, rowq, pm, steps, desc);
+                     c_col, c_off, cin_off, pptr, px, py, rs, cs, rowq, pm, steps, desc);
   return hipGetLastError();
 }
 
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
-                                const int64_t* chs, const int32_t* blk2tile, const int64_t* sbase,
-                                const int32_t* c_col, const int32_t* cs, const int64_t* px, const int64_t* py,
-                                const PieceMap& pm, uint64_t* steps) {
+                                const int32_t* blk2tile, const int64_t* sbase, const int32_t* c_col,
+                                const int32_t* cs, const int64_t* px, const int64_t* py, const PieceMap& pm,
+                                uint64_t* steps) {
   if (nprod == 0) return hipSuccess;
   hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, pblk, pptr,
-                     chs, blk2tile, sbase, c_col, cs, px, py, pm, steps);
+                     blk2tile, sbase, c_col, cs, px, py, pm, steps);
   return hipGetLastError();
 }
 
