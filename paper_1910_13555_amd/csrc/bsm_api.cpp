@@ -207,8 +207,8 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, cb.cls);
     pl->xb = DBuf<int32_t>(ctx, 9 * kClasses);
     hip_check(launch_xcd_bounds(st, pl->sdesc.p, nullptr, cb, pl->xb.p), "XCD shares");
-    hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, b2t.p, sb.p, pl->c_col.p,
-                                   pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
+    hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, b2t.p, sb.p, pl->c_row.p, pl->c_col.p,
+                                   pl->c_rs, pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
               "product steps");
   }
   ctx->mark(ctx->plan_ev[3]);

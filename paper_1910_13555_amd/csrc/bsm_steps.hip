@@ -62,7 +62,7 @@ __device__ __forceinline__ void step_words(int64_t xb, int64_t yb, int K, int N,
 // Per tile: its step count, the sum over its block's products of
 // ceil(K / L) (one step for a tile without products; split plans: padded to
 // even length, two steps without products); blk2tile[t] = w for blocks that
-// are a single tile, -1 otherwise.
+// are a single tile (other entries are not written).
 __global__ void k_tile_steps(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ pptr,
                              const int64_t* __restrict__ px, int L, const int32_t* __restrict__ c_row,
                              const int32_t* __restrict__ c_col, const int32_t* __restrict__ rs,
@@ -137,15 +137,16 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
 // steps of the block's earlier products.
 __global__ void k_product_steps(int64_t nprod, const int32_t* __restrict__ pblk, const int64_t* __restrict__ pptr,
                                 const int32_t* __restrict__ blk2tile, const int64_t* __restrict__ sbase,
-                                const int32_t* __restrict__ c_col, const int32_t* __restrict__ cs,
+                                const int32_t* __restrict__ c_row, const int32_t* __restrict__ c_col,
+                                const int32_t* __restrict__ rs, const int32_t* __restrict__ cs,
                                 const int64_t* __restrict__ px, const int64_t* __restrict__ py, PieceMap pm,
                                 uint64_t* __restrict__ steps) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprod) return;
   const int64_t t = pblk[p];          // the block of product p
-  const int w = blk2tile[t];
-  if (w < 0) return;
   const int N = cs[c_col[t]];
+  if (rs[c_row[t]] > kTile || N > kTile) return;   // written by its tiles' work-item threads
+  const int w = blk2tile[t];
   const int L = step_k_len(pm.apad != nullptr);
   int64_t s = sbase[w];
   for (int64_t q = pptr[t]; q < p; ++q) s += ((int)((uint64_t)px[q] >> 48) + L - 1) / L;
@@ -156,21 +157,12 @@ __global__ void k_product_steps(int64_t nprod, const int32_t* __restrict__ pblk,
   for (int k0 = 0; k0 < K; k0 += L, ++s) step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
 }
 
-__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 }  // namespace
 
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
                              const int64_t* px, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
                              const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile) {
-  if (nblk > 0) {
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, blk2tile, nblk, -1);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+  (void)nblk;
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_steps, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, pptr, px,
                      step_k_len(split), c_row, c_col, rs, cs, (int)split, nsteps, blk2tile);
@@ -189,12 +181,12 @@ hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, c
 }
 
 hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
-                                const int32_t* blk2tile, const int64_t* sbase, const int32_t* c_col,
-                                const int32_t* cs, const int64_t* px, const int64_t* py, const PieceMap& pm,
-                                uint64_t* steps) {
+                                const int32_t* blk2tile, const int64_t* sbase, const int32_t* c_row,
+                                const int32_t* c_col, const int32_t* rs, const int32_t* cs, const int64_t* px,
+                                const int64_t* py, const PieceMap& pm, uint64_t* steps) {
   if (nprod == 0) return hipSuccess;
   hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, pblk, pptr,
-                     blk2tile, sbase, c_col, cs, px, py, pm, steps);
+                     blk2tile, sbase, c_row, c_col, rs, cs, px, py, pm, steps);
   return hipGetLastError();
 }
 
