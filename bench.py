@@ -517,7 +517,18 @@ def main():
         del plan2, out2
     phases = [round(sorted(p[i] for p in ph)[2], 4) for i in range(4)]
     ctx.set_timing(False)
-    del evict
+    # the same steps back to back without the eviction (operands left in the
+    # Infinity Cache by the previous step), for comparison with measurements
+    # taken that way
+    plan2 = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan2 = None
+        plan2, out2 = step()
+    torch.cuda.synchronize()
+    ms_warm = (time.perf_counter() - t0) * 1e3 / args.steps
+    del plan2, out2, evict
 
     # numeric phase alone (plan reuse, as in repeated multiplies with a fixed pattern)
     reuse_ms = time_events(lambda: plan.execute(1.0, A.values, B.values, 0.0, None, out), args.steps,
@@ -536,6 +547,7 @@ def main():
         "ms_per_step": ms_step,
         "ms_per_step_median": float(sorted(per_step)[len(per_step) // 2]),
         "ms_per_step_min": float(min(per_step)),
+        "ms_per_step_back_to_back_no_eviction": ms_warm,
         "phase_ms": {"norms": phases[0], "symbolic": phases[1], "step_lists": phases[2], "numeric": phases[3]},
         "higher_is_better": True,
         "scaling": "weak",
