@@ -421,8 +421,10 @@ bsm_status bsm_plan_t3_pattern(bsm_plan plan, bsm_tpattern* out);
  * launch; the autotuner (paper_1910_13555_amd/tune.py) measures both per
  * class and writes a JSON file {"variant": [16 integers], ...}.
  * bsm_tune_load(path) reads such a file (BSM_E_INVALID if unreadable or
- * malformed); path NULL restores the built-in defaults (16x16x4 where both
- * padded edges are multiples of 16; canonical work order). */
+ * malformed, and then nothing changes); path NULL restores the built-in
+ * defaults (16x16x4 where both padded edges are multiples of 16; canonical
+ * work order, runs of 1, one wavefront per workgroup).  The optional scalar
+ * fields "run" and "group" are read at their first occurrence in the file. */
 bsm_status bsm_tune_load(const char* path);
 /* Work order of the numeric phase: output tiles of a class are visited in
  * panels of rows x cols output blocks (panels row by row, canonical order

@@ -908,7 +908,9 @@ bsm_status bsm_tune_load(const char* path) {
         while (*q == ',' || *q == ' ' || *q == '\n' || *q == '\t' || *q == '\r') ++q;
       }
     }
-    if (!set_variants(v)) fail(BSM_E_INVALID, "variants must be 0 or 1");
+    // every field is checked before any is applied: a rejected file changes nothing
+    for (int c = 0; c < kClasses; ++c)
+      if (v[c] != 0 && v[c] != 1) fail(BSM_E_INVALID, "variants must be 0 or 1");
     int32_t panel[2] = {0, 0};
     if (path) {
       const size_t pk = text.find("\"panel\"");
@@ -925,8 +927,6 @@ bsm_status bsm_tune_load(const char* path) {
         }
       }
     }
-    g_panel[0] = panel[0];
-    g_panel[1] = panel[1];
     // scalar fields: the first occurrence of the key (the tuner writes them
     // before its list of trials)
     auto int_field = [&](const char* key, long lo, long hi, long dflt) {
@@ -942,6 +942,9 @@ bsm_status bsm_tune_load(const char* path) {
     const int32_t run = (int32_t)int_field("run", 1, 4096, 1);
     const int32_t wpg = (int32_t)int_field("group", 1, kMaxGroupWaves, 1);
     if (wpg & (wpg - 1)) fail(BSM_E_INVALID, "%s: \"group\" must be a power of two", path);
+    set_variants(v);
+    g_panel[0] = panel[0];
+    g_panel[1] = panel[1];
     g_run = run;
     g_wpg = wpg;
   });

@@ -140,10 +140,33 @@ def test_tuning_table_roundtrip(tmp_path):
         f.write_text('{"variant": [0, 1, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 1, 1, 1, 1], "panel": [64, 16]}')
         bsm.bsm_tune_load(f)
         assert bsm.bsm_tune_get_panel() == (64, 16)
+        assert bsm.bsm_tune_get_run() == 1 and bsm.bsm_tune_get_group() == 1   # absent: reset
+        # the work-order scalars, written before the tuner's trials (whose own
+        # "run" / "group" entries come later in the file and are not read)
+        f.write_text('{"variant": [0] * 16, "run": 8, "group": 4, '
+                     '"trials": [{"run": 2, "ms": 1.0}, {"group": 8, "ms": 1.0}]}'.replace("[0] * 16", str([0] * 16)))
+        bsm.bsm_tune_load(f)
+        assert bsm.bsm_tune_get_run() == 8 and bsm.bsm_tune_get_group() == 4
+        bsm.bsm_tune_run(3)
+        bsm.bsm_tune_group(2)
+        assert bsm.bsm_tune_get_run() == 3 and bsm.bsm_tune_get_group() == 2
+        for text in ('"run": 0', '"run": 5000', '"group": 3', '"group": 16', '"group": 0'):
+            bad.write_text('{"variant": %s, "panel": [8, 8], %s}' % ([1] * 16, text))
+            with pytest.raises(bsm.BsmError):
+                bsm.bsm_tune_load(bad)
+            # a rejected file changes nothing
+            assert bsm.bsm_tune_get() == [0] * 16 and bsm.bsm_tune_get_panel() == (0, 0)
+            assert bsm.bsm_tune_get_run() == 3 and bsm.bsm_tune_get_group() == 2
+        for v in (0, 3, 16):
+            with pytest.raises(bsm.BsmError):
+                bsm.bsm_tune_group(v)
+        with pytest.raises(bsm.BsmError):
+            bsm.bsm_tune_run(0)
     finally:
         bsm.bsm_tune_load(None)
     assert bsm.bsm_tune_get() == default
     assert bsm.bsm_tune_get_panel() == (0, 0)
+    assert bsm.bsm_tune_get_run() == 1 and bsm.bsm_tune_get_group() == 1
 
 
 def test_ctx_create_ex_needs_both_callbacks():
