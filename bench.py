@@ -41,8 +41,14 @@ KERNEL_NAME = "bsm::k_numeric<false, false, false, {}>"
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the numeric kernels' source and of the tile-class table that
+    decides which classes each kernel family serves: the recorded traffic of
+    a family holds only while both are unchanged."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, TUNED):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(kernel):
