@@ -585,6 +585,11 @@ __device__ __forceinline__ void run_steps(const NumParams& P, int e0, int e1, in
     const bool live = it < e1;
     const uint64_t w0 = ((uint64_t)rec[1] << 32) | rec[0];
     const uint64_t w1 = ((uint64_t)rec[3] << 32) | rec[2];
+    // Scalar loads may complete out of order, so any wait for one of them
+    // waits for all: wait here, for the loads of earlier steps (long done),
+    // before the new record load, so that the wait the compiler places for
+    // this step's record does not also cover the load issued just now.
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vector memory and export counts not waited
     // the record for this buffer's next step, D steps ahead
     rec = load_rec();
     padvance();
