@@ -199,6 +199,10 @@ __device__ __forceinline__ void run_split_steps(const NumParams& P, int e0, int 
     const uint32_t w1lo = sp ? rec[6] : rec[2], w1hi = sp ? rec[7] : rec[3];
     const uint64_t w0 = ((uint64_t)w0hi << 32) | w0lo;
     const uint64_t w1 = ((uint64_t)w1hi << 32) | w1lo;
+    // wait for the earlier scalar loads before issuing the next record load,
+    // so that no later wait of this step covers the new load (scalar loads
+    // may complete out of order: any wait for one waits for all)
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0) only
     rec = load_rec();
     padvance();
     // rows of A and columns of B are padded with zeros to Kp (a multiple of
