@@ -199,17 +199,13 @@ void plan_symbolic(bsm_plan pl, const double* a_vals, const double* a_norms, con
     hip_check(launch_scan(st, 1, pl->ntasks, ns.p, sb.p, nullptr, scr2.p), "step scan");
     pl->steps = DBuf<uint64_t>(ctx, 2 * pl->nsteps);
     pl->sdesc = DBuf<TaskDesc>(ctx, pl->ntasks);
-    hip_check(launch_tile_items(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
-                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs,
-                                pl->rowq.p, pm, pl->steps.p, pl->sdesc.p),
-              "work items");
     ClassBounds cb;
     std::copy(pl->cls_tile, pl->cls_tile + kClasses + 1, cb.cls);
     pl->xb = DBuf<int32_t>(ctx, 9 * kClasses);
-    hip_check(launch_xcd_bounds(st, pl->sdesc.p, nullptr, cb, pl->xb.p), "XCD shares");
-    hip_check(launch_product_steps(st, pl->nprod, pblk.p, pl->pptr.p, b2t.p, sb.p, pl->c_row.p, pl->c_col.p,
-                                   pl->c_rs, pl->c_cs, pl->px.p, pl->py.p, pm, pl->steps.p),
-              "product steps");
+    hip_check(launch_step_lists(st, (int32_t)pl->ntasks, pl->tasks.p, sb.p, pl->c_row.p, pl->c_col.p, pl->c_off.p,
+                                pl->cin_off.p, pl->pptr.p, pl->px.p, pl->py.p, pl->c_rs, pl->c_cs, pl->rowq.p, pm,
+                                pl->nprod, pblk.p, b2t.p, cb, pl->steps.p, pl->sdesc.p, pl->xb.p),
+              "step lists");
   }
   ctx->mark(ctx->plan_ev[3]);
   ctx->plan_timed = ctx->timing;

@@ -1,4 +1,5 @@
-// Device helpers shared by the numeric kernels (bsm_numeric.hip, bsm_split.hip).
+// Device helpers shared by the numeric kernels (bsm_numeric.hip, bsm_split.hip)
+// and the step-list builder (bsm_steps.hip).
 #pragma once
 
 #include "bsm_internal.h"
@@ -106,9 +107,38 @@ __device__ __forceinline__ int slice_start(const TaskDesc* desc, int64_t d0, int
   return (int)s;
 }
 
+// Steps before work item i of a class whose items end at d1: from the
+// step prefix wpre when given, else from the items' own step ranges.
+__device__ __forceinline__ int64_t steps_before(const TaskDesc* d, const int64_t* wpre, int i, int d1) {
+  if (wpre) return wpre[i];
+  if (i < d1) return d[i].pbeg;
+  return d[d1 - 1].pbeg + d[d1 - 1].np;
+}
+
+// Entry t (< 9 kClasses) of the XCD share bounds: class c = t / 9, bound
+// x = t % 9 -- the first item of class c at or past x eighths of its steps.
+__device__ __forceinline__ void xcd_bound_entry(const TaskDesc* desc, const int64_t* wpre, const ClassBounds& cb,
+                                                int t, int32_t* xb) {
+  const int c = t / 9, x = t % 9;
+  const int d0 = cb.cls[c], d1 = cb.cls[c + 1];
+  int r = x == 0 ? d0 : d1;
+  if (x > 0 && x < 8 && d1 > d0) {
+    const int64_t w0 = steps_before(desc, wpre, d0, d1), w1 = steps_before(desc, wpre, d1, d1);
+    const int64_t target = w0 + (w1 - w0) * x / 8;
+    int lo = d0, hi = d1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (steps_before(desc, wpre, mid, d1) >= target) hi = mid; else lo = mid + 1;
+    }
+    r = lo;
+  }
+  xb[t] = r;
+}
+
 // Row-major path: the XCD shares of a class's items, computed once per plan
-// or batch (bsm_numeric.hip): items [xb[9c + x], xb[9c + x + 1]) of class c
-// go to XCD x, each share holding an eighth of the class's steps.
+// (with the step lists, bsm_steps.hip) or batch (bsm_numeric.hip): items
+// [xb[9c + x], xb[9c + x + 1]) of class c go to XCD x, each share holding an
+// eighth of the class's steps.
 __device__ __forceinline__ int xcd_bound(const NumParams& P, int c, int x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return cptr(P.xb)[__builtin_amdgcn_readfirstlane(9 * c + x)];

@@ -196,16 +196,16 @@ struct PieceMap {
 hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const int2* tiles, const int64_t* pptr,
                              const int64_t* px, const int32_t* c_row, const int32_t* c_col, const int32_t* rs,
                              const int32_t* cs, bool split, int64_t* nsteps, int32_t* blk2tile);
-hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
+struct ClassBounds;
+// The work items, the steps and the XCD share bounds, once the step prefix
+// sbase (ntiles + 1 entries) is known; one launch.
+hipError_t launch_step_lists(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
                              const int32_t* rs, const int32_t* cs,
                              const int32_t* rowq /* output split factor per block row, or null */,
-                             const PieceMap& pm, uint64_t* steps, TaskDesc* desc);
-hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
-                                const int32_t* blk2tile, const int64_t* sbase, const int32_t* c_row,
-                                const int32_t* c_col, const int32_t* rs, const int32_t* cs, const int64_t* px,
-                                const int64_t* py, const PieceMap& pm, uint64_t* steps);
+                             const PieceMap& pm, int64_t nprod, const int32_t* pblk, const int32_t* blk2tile,
+                             const ClassBounds& cb, uint64_t* steps, TaskDesc* desc, int32_t* xb);
 // bsm_numeric.hip
 // Numeric phase: two persistent launches (tiles up to 24x24, then 32-wide).
 hipError_t launch_numeric(hipStream_t s, bool generic, const NumParams& p);

@@ -124,30 +124,9 @@ hipError_t launch_desc_steps(hipStream_t s, const TaskDesc* d, int64_t n, int64_
   return hipGetLastError();
 }
 
-__device__ __forceinline__ int64_t steps_before(const TaskDesc* d, const int64_t* wpre, int i, int d1) {
-  if (wpre) return wpre[i];
-  if (i < d1) return d[i].pbeg;
-  return d[d1 - 1].pbeg + d[d1 - 1].np;
-}
-
 __global__ void k_xcd_bounds(const TaskDesc* __restrict__ desc, const int64_t* __restrict__ wpre, ClassBounds cb,
                              int32_t* __restrict__ xb) {
-  const int t = threadIdx.x;
-  if (t >= 9 * kClasses) return;
-  const int c = t / 9, x = t % 9;
-  const int d0 = cb.cls[c], d1 = cb.cls[c + 1];
-  int r = x == 0 ? d0 : d1;
-  if (x > 0 && x < 8 && d1 > d0) {
-    const int64_t w0 = steps_before(desc, wpre, d0, d1), w1 = steps_before(desc, wpre, d1, d1);
-    const int64_t target = w0 + (w1 - w0) * x / 8;
-    int lo = d0, hi = d1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (steps_before(desc, wpre, mid, d1) >= target) hi = mid; else lo = mid + 1;
-    }
-    r = lo;
-  }
-  xb[t] = r;
+  if (threadIdx.x < 9 * kClasses) xcd_bound_entry(desc, wpre, cb, (int)threadIdx.x, xb);
 }
 
 hipError_t launch_xcd_bounds(hipStream_t s, const TaskDesc* desc, const int64_t* wpre, const ClassBounds& cb,

@@ -12,7 +12,7 @@
 // Split-precision plans pair the steps of a tile (one bfloat16 instruction
 // takes two): their step lists are padded to even length with empty steps
 // (all-zero records, kv = 0).
-#include "bsm_internal.h"
+#include "bsm_device.h"
 
 namespace bsm {
 
@@ -78,18 +78,45 @@ __global__ void k_tile_steps(int32_t ntiles, const int2* __restrict__ tiles, con
   if (single) blk2tile[t] = w;
 }
 
-// Per tile: the work item; the steps of tiles of multi-tile blocks
+// The arrays the step-list passes read and write.
+struct StepArgs {
+  int32_t ntiles;
+  int64_t nprod;
+  const int2* tiles;
+  const int64_t* sbase;     // step prefix over the tiles (ntiles + 1 entries)
+  const int32_t* c_row;
+  const int32_t* c_col;
+  const int64_t* c_off;
+  const int64_t* cin_off;
+  const int64_t* pptr;
+  const int64_t* px;
+  const int64_t* py;
+  const int32_t* rs;
+  const int32_t* cs;
+  const int32_t* rowq;
+  const int32_t* pblk;      // output block of every product
+  const int32_t* blk2tile;  // the tile of every single-tile output block
+  PieceMap pm;
+  uint64_t* steps;
+  TaskDesc* desc;
+  int32_t* xb;              // XCD share bounds, 9 per class
+};
+
+// Tile w: the work item; the steps of tiles of multi-tile blocks
 // (serially, those are rare); the empty steps (the one of a tile without
 // products, or a split plan's padding).
-__global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, const int64_t* __restrict__ sbase,
-                             const int32_t* __restrict__ c_row, const int32_t* __restrict__ c_col,
-                             const int64_t* __restrict__ c_off, const int64_t* __restrict__ cin_off,
-                             const int64_t* __restrict__ pptr, const int64_t* __restrict__ px,
-                             const int64_t* __restrict__ py, const int32_t* __restrict__ rs,
-                             const int32_t* __restrict__ cs, const int32_t* __restrict__ rowq, PieceMap pm,
-                             uint64_t* __restrict__ steps, TaskDesc* __restrict__ desc) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= ntiles) return;
+__device__ __forceinline__ void tile_item(const StepArgs& a, int w) {
+  const int2* __restrict__ tiles = a.tiles;
+  const int64_t* __restrict__ sbase = a.sbase;
+  const int32_t* __restrict__ c_row = a.c_row;
+  const int32_t* __restrict__ c_col = a.c_col;
+  const int32_t* __restrict__ rs = a.rs;
+  const int32_t* __restrict__ cs = a.cs;
+  const int64_t* __restrict__ pptr = a.pptr;
+  const int64_t* __restrict__ px = a.px;
+  const int64_t* __restrict__ py = a.py;
+  const PieceMap& pm = a.pm;
+  uint64_t* __restrict__ steps = a.steps;
   const int t = tiles[w].x;
   const int tr = tiles[w].y & 0xffff, tc = tiles[w].y >> 16;
   const int i = c_row[t], j = c_col[t];
@@ -100,18 +127,18 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
   int64_t s = sbase[w];
   TaskDesc d;
   d.pbeg = s;
-  d.cout = c_off[t];
-  d.cin = cin_off ? cin_off[t] : -1;
+  d.cout = a.c_off[t];
+  d.cin = a.cin_off ? a.cin_off[t] : -1;
   d.np = (int32_t)(sbase[w + 1] - s);
   d.flags = kTaskFirst | kTaskLast | (p0 == p1 ? kTaskEmpty : 0);
   d.M = (uint16_t)M;
   d.N = (uint16_t)N;
   d.tr = (uint16_t)tr;
   d.tc = (uint16_t)tc;
-  d.qo = (uint16_t)(rowq ? rowq[i] : 1);
+  d.qo = (uint16_t)(a.rowq ? a.rowq[i] : 1);
   d.cls = (uint16_t)tile_class(mt, nt);
   d.pid = 0;
-  desc[w] = d;
+  a.desc[w] = d;
   const int L = step_k_len(pm.apad != nullptr);
   const bool single = M <= kTile && N <= kTile;   // steps written per product
   for (int64_t p = p0; p < p1; ++p) {
@@ -133,28 +160,40 @@ __global__ void k_tile_items(int32_t ntiles, const int2* __restrict__ tiles, con
   }
 }
 
-// Per product of a single-tile block: its steps at the tile's base plus the
+// Product p of a single-tile block: its steps at the tile's base plus the
 // steps of the block's earlier products.
-__global__ void k_product_steps(int64_t nprod, const int32_t* __restrict__ pblk, const int64_t* __restrict__ pptr,
-                                const int32_t* __restrict__ blk2tile, const int64_t* __restrict__ sbase,
-                                const int32_t* __restrict__ c_row, const int32_t* __restrict__ c_col,
-                                const int32_t* __restrict__ rs, const int32_t* __restrict__ cs,
-                                const int64_t* __restrict__ px, const int64_t* __restrict__ py, PieceMap pm,
-                                uint64_t* __restrict__ steps) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprod) return;
-  const int64_t t = pblk[p];          // the block of product p
-  const int N = cs[c_col[t]];
-  if (rs[c_row[t]] > kTile || N > kTile) return;   // written by its tiles' work-item threads
-  const int w = blk2tile[t];
-  const int L = step_k_len(pm.apad != nullptr);
-  int64_t s = sbase[w];
-  for (int64_t q = pptr[t]; q < p; ++q) s += ((int)((uint64_t)px[q] >> 48) + L - 1) / L;
-  const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)py[p];
+__device__ __forceinline__ void product_step(const StepArgs& a, int64_t p) {
+  const int64_t* __restrict__ px = a.px;
+  const int64_t t = a.pblk[p];        // the block of product p
+  const int N = a.cs[a.c_col[t]];
+  if (a.rs[a.c_row[t]] > kTile || N > kTile) return;   // written by its tiles' work-item threads
+  const int w = a.blk2tile[t];
+  const int L = step_k_len(a.pm.apad != nullptr);
+  int64_t s = a.sbase[w];
+  for (int64_t q = a.pptr[t]; q < p; ++q) s += ((int)((uint64_t)px[q] >> 48) + L - 1) / L;
+  const uint64_t xw = (uint64_t)px[p], yw = (uint64_t)a.py[p];
   int64_t xb, yb;
-  product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), pm, xb, yb);
+  product_bases((int64_t)(xw & kMask48), (int64_t)(yw & kMask48), a.pm, xb, yb);
   const int K = (int)(xw >> 48);
-  for (int k0 = 0; k0 < K; k0 += L, ++s) step_words(xb, yb, K, N, 0, 0, k0, pm.apad != nullptr, steps + 2 * s);
+  for (int k0 = 0; k0 < K; k0 += L, ++s) step_words(xb, yb, K, N, 0, 0, k0, a.pm.apad != nullptr, a.steps + 2 * s);
+}
+
+// The step lists once the step prefix is known, in one launch (the three
+// parts are independent): workgroups [0, bt) one thread per tile (work
+// items), [bt, bt + bp) one thread per product (the steps of single-tile
+// blocks), and the last one the XCD share bounds, from the step prefix.
+constexpr int kStepThreads = 256;
+__global__ void __launch_bounds__(kStepThreads) k_step_lists(StepArgs a, int32_t bt, int32_t bp, ClassBounds cb) {
+  const int b = blockIdx.x;
+  if (b < bt) {
+    const int w = b * kStepThreads + threadIdx.x;
+    if (w < a.ntiles) tile_item(a, w);
+  } else if (b < bt + bp) {
+    const int64_t p = (int64_t)(b - bt) * kStepThreads + threadIdx.x;
+    if (p < a.nprod) product_step(a, p);
+  } else if (threadIdx.x < 9 * kClasses) {
+    xcd_bound_entry(nullptr, a.sbase, cb, (int)threadIdx.x, a.xb);
+  }
 }
 
 }  // namespace
@@ -169,26 +208,22 @@ hipError_t launch_tile_steps(hipStream_t s, int32_t ntiles, int64_t nblk, const 
   return hipGetLastError();
 }
 
-hipError_t launch_tile_items(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
+hipError_t launch_step_lists(hipStream_t s, int32_t ntiles, const int2* tiles, const int64_t* sbase,
                              const int32_t* c_row, const int32_t* c_col, const int64_t* c_off,
                              const int64_t* cin_off, const int64_t* pptr, const int64_t* px, const int64_t* py,
                              const int32_t* rs, const int32_t* cs, const int32_t* rowq, const PieceMap& pm,
-                             uint64_t* steps, TaskDesc* desc) {
-  if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_items, dim3((ntiles + 255) / 256), dim3(256), 0, s, ntiles, tiles, sbase, c_row,
-                     c_col, c_off, cin_off, pptr, px, py, rs, cs, rowq, pm, steps, desc);
+                             int64_t nprod, const int32_t* pblk, const int32_t* blk2tile, const ClassBounds& cb,
+                             uint64_t* steps, TaskDesc* desc, int32_t* xb) {
+  StepArgs a;
+  a.ntiles = ntiles; a.nprod = nprod; a.tiles = tiles; a.sbase = sbase; a.c_row = c_row; a.c_col = c_col;
+  a.c_off = c_off; a.cin_off = cin_off; a.pptr = pptr; a.px = px; a.py = py; a.rs = rs; a.cs = cs; a.rowq = rowq;
+  a.pblk = pblk; a.blk2tile = blk2tile; a.pm = pm; a.steps = steps; a.desc = desc; a.xb = xb;
+  const int64_t bt = (ntiles + kStepThreads - 1) / kStepThreads;
+  const int64_t bp = (nprod + kStepThreads - 1) / kStepThreads;
+  if (bt + bp + 1 > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step_lists, dim3((unsigned)(bt + bp + 1)), dim3(kStepThreads), 0, s, a, (int32_t)bt,
+                     (int32_t)bp, cb);
   return hipGetLastError();
 }
-
-hipError_t launch_product_steps(hipStream_t s, int64_t nprod, const int32_t* pblk, const int64_t* pptr,
-                                const int32_t* blk2tile, const int64_t* sbase, const int32_t* c_row,
-                                const int32_t* c_col, const int32_t* rs, const int32_t* cs, const int64_t* px,
-                                const int64_t* py, const PieceMap& pm, uint64_t* steps) {
-  if (nprod == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_product_steps, dim3((unsigned)((nprod + 255) / 256)), dim3(256), 0, s, nprod, pblk, pptr,
-                     blk2tile, sbase, c_row, c_col, rs, cs, px, py, pm, steps);
-  return hipGetLastError();
-}
-
 
 }  // namespace bsm
