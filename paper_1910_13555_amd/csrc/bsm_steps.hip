@@ -1,6 +1,7 @@
 // Step lists of the row-major numeric path.  A step is one product's k range
-// [k0, k0 + L) for one output tile (L = step_k_len: 8 for float64 plans, 16
-// for split precision); its record holds everything the kernel
+// [k0, k0 + L) for one output tile (L = step_k_len, 16; the float64 kernels
+// take it as four instruction k-steps of 4, the split-precision ones as half
+// of a bfloat16 instruction's 32); its record holds everything the kernel
 // needs to address that step's operands, so the kernel's per-step work is a
 // few scalar instructions (Sec. 2's stacks, expanded to the granularity of
 // the matrix-core k-steps):
